@@ -1,0 +1,187 @@
+/*
+ * svmhip.h -- C-ABI of libsvmhip.so, an SMO trainer for two-class soft-margin
+ * RBF support vector machines on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: the parallel SMO with adaptive shrinking of Narasimhan, Vishnu,
+ * Holder and Hoisie ("Fast Support Vector Machines Using Parallel Adaptive
+ * Shrinking on Distributed Systems").  The library solves the Wolfe dual
+ * (eq:lagdual with the constraints of eq:eqconst):
+ *
+ *     max_alpha  sum_i alpha_i - 1/2 sum_ij alpha_i alpha_j y_i y_j K(x_i, x_j)
+ *     s.t.       0 <= alpha_i <= C,  sum_i alpha_i y_i = 0
+ *
+ * with the Gaussian kernel K(x, z) = exp(-gamma * ||x - z||^2), gamma = 1/(2 sigma^2)
+ * (Section "Datasets").  It maintains f_i = sum_j alpha_j y_j K_ij - y_i
+ * (eq:fcache, the paper's gamma_i), selects the two worst violators b_up /
+ * b_low (eq:bminmax) with the lowest sample index on ties, updates the pair
+ * (eq:alphaup, eq:rho) and stops when b_low - b_up <= 2 eps (eq:kktterm).
+ * Shrinking follows eq:shrink with the schedules of Table 3 and the driver of
+ * Alg. 5 (single reconstruction) or its multi-reconstruction variant;
+ * shrunk samples get their f back by gradient reconstruction (Alg. 6).
+ *
+ * Conventions for every entry point:
+ *   - every array argument is a DEVICE pointer unless it is marked "host";
+ *   - the caller owns every buffer; the library never frees caller memory;
+ *   - `stream` is a hipStream_t (NULL = the default stream); calls are
+ *     stream-ordered and return after the host-visible outputs are written;
+ *   - return value: 0 = SVM_OK, > 0 = warning (the outputs are consistent),
+ *     < 0 = error (outputs undefined); svm_strerror() gives the text.
+ *   - calls are not re-entrant on one workspace; distinct workspaces may be
+ *     used from distinct host threads.
+ */
+#ifndef SVMHIP_H
+#define SVMHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes */
+#define SVM_OK 0
+#define SVM_NOT_CONVERGED 1      /* max_iter reached; alpha, f and the result are consistent */
+#define SVM_EINVAL (-1)          /* bad argument: sizes, C/gamma/eps <= 0, labels not +-1, bad CSR */
+#define SVM_EONECLASS (-2)       /* only one class present in y */
+#define SVM_ENONFINITE (-3)      /* NaN or Inf in the sample values */
+#define SVM_EWORKSPACE (-4)      /* workspace too small or misaligned */
+#define SVM_EHIP (-5)            /* a HIP runtime call failed */
+#define SVM_EUNSUPPORTED (-6)    /* shape outside what this build handles (e.g. CSR row too long) */
+#define SVM_ENOMEM (-7)          /* an internal allocation failed (server budget exhausted, ...) */
+#define SVM_EBUSY (-8)           /* serving: the ticket is still running */
+#define SVM_EABORT (-9)          /* the device loop stopped on its watchdog (barrier wait timed out) */
+
+/* ---- sample layouts */
+#define SVM_DENSE_ROW_MAJOR 0     /* x[i*ldx + k], ldx >= d */
+#define SVM_DENSE_FEATURE_MAJOR 1 /* x[k*ldx + i], ldx >= n */
+#define SVM_CSR 2                 /* row_ptr[n+1], col/val[nnz]; columns sorted, unique, in [0, d) */
+
+/* ---- shrinking (Table 3): mode and schedule */
+#define SVM_SHRINK_NONE 0         /* Alg. 2 "Original": no shrinking */
+#define SVM_SHRINK_SINGLE 1       /* Alg. 5: shrink until 20 eps, reconstruct once, finish unshrunk */
+#define SVM_SHRINK_MULTI 2        /* multi-reconstruction variant: reconstruct whenever the active set meets the tolerance */
+#define SVM_KIND_FIXED 0          /* "random: k": shrink every k iterations (k = shrink_param) */
+#define SVM_KIND_FRACTION 1       /* "numsamples": first shrink after ceil(shrink_param * n) iterations */
+
+/* ---- kernel-value precision */
+#define SVM_KERNEL_FP32 0         /* kernel values in FP32; f, alpha, thresholds, KKT test in FP64 */
+#define SVM_KERNEL_FP64 1         /* everything in FP64 (follows the FP64 reference trajectory) */
+
+/* ---- flags */
+#define SVM_FLAG_WARM_START 1u         /* alpha and f are inputs: f must equal eq:fcache for alpha */
+#define SVM_FLAG_NO_FINAL_RECOMPUTE 2u /* skip the closing FP64-accumulated recompute of f and KKT re-check */
+
+/* A labelled (or, for queries, unlabelled) sample set.  All pointers are device pointers. */
+typedef struct {
+    int32_t n;                /* samples, >= 1 (training: >= 2) */
+    int32_t d;                /* features, >= 1 */
+    int32_t layout;           /* SVM_DENSE_ROW_MAJOR | SVM_DENSE_FEATURE_MAJOR | SVM_CSR */
+    int32_t reserved;
+    const float* x;           /* dense values */
+    int64_t ldx;              /* dense leading dimension (elements) */
+    const int32_t* row_ptr;   /* CSR */
+    const int32_t* col;       /* CSR */
+    const float* val;         /* CSR; values read as given */
+    const int8_t* y;          /* labels +1 / -1 (may be NULL for query sets) */
+} svm_problem_t;
+
+typedef struct {
+    double C;                 /* box bound, > 0 */
+    double gamma;             /* RBF width 1/(2 sigma^2), > 0 */
+    double eps;               /* tolerance: stop when b_low - b_up <= 2 eps */
+    int32_t shrink_mode;      /* SVM_SHRINK_* */
+    int32_t shrink_kind;      /* SVM_KIND_* */
+    double shrink_param;      /* k (fixed) or fraction of n */
+    int64_t max_iter;         /* iteration cap (> 0); reaching it returns SVM_NOT_CONVERGED */
+    int32_t kernel_precision; /* SVM_KERNEL_FP32 | SVM_KERNEL_FP64 */
+    uint32_t flags;           /* SVM_FLAG_* */
+    int32_t grid_blocks;      /* 0 = choose automatically; else the number of workgroups of the step */
+    int32_t lanes_per_row;    /* 0 = choose automatically; CSR lanes per row (1, 2, 4, 8, 16, 32, 64) */
+} svm_params_t;
+
+typedef struct {
+    double beta;              /* threshold: mean f over I0, else (b_up + b_low)/2 */
+    double b_up, b_low;       /* final thresholds over all samples */
+    double dual_obj;          /* sum alpha - 1/2 sum alpha_i y_i (f_i + y_i) */
+    int64_t iterations;       /* SMO pair updates */
+    int32_t n_sv, n_bsv;      /* alpha > 0, alpha == C */
+    int32_t n_recon;          /* gradient reconstructions (Alg. 6) */
+    int32_t status;           /* SVM_OK or SVM_NOT_CONVERGED */
+    int64_t shrink_passes;    /* iterations on which the shrink rule ran */
+    int64_t shrunk_total;     /* samples removed over all shrink passes */
+    int32_t n_launches;       /* persistent-loop launches (phases) */
+    int32_t grid_blocks;      /* workgroups used by the step */
+    double ms_total;          /* wall time of the call (host clock) */
+    double ms_step;           /* time in the persistent SMO loop */
+    double ms_recon;          /* time in reconstruction / recompute */
+} svm_result_t;
+
+/* Bytes of device workspace svm_train needs for this problem (256-byte aligned). */
+size_t svm_train_workspace_size(const svm_problem_t* prob, const svm_params_t* params);
+
+/* Train on `prob` (labels required).  alpha: n doubles (output; input with
+ * SVM_FLAG_WARM_START).  f: n doubles or NULL (output: f_i of eq:fcache).
+ * out: host struct.  workspace/ws_bytes: device buffer of at least
+ * svm_train_workspace_size() bytes, or NULL/0 to let the library allocate and
+ * free one itself.  The inputs are validated on the device first
+ * (SVM_EINVAL / SVM_EONECLASS / SVM_ENONFINITE). */
+int svm_train(const svm_problem_t* prob, const svm_params_t* params, double* alpha, double* f,
+              svm_result_t* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Decision values out[q] = sum_j alpha_j y_j K(x_j, z_q) - beta (eq:classi
+ * before the sign; the class is +1 when the value is >= 0).  train: the
+ * training set (labels required); alpha: n doubles; queries: nq samples of
+ * the same d (labels ignored); out: nq doubles.  kernel_precision as in
+ * svm_params_t.  Allocates its scratch on `stream` (stream-ordered). */
+int svm_decision(const svm_problem_t* train, const double* alpha, double beta, double gamma,
+                 const svm_problem_t* queries, double* out, int32_t kernel_precision, void* stream);
+
+/* Several independent problems in one persistent fused launch: problem p is
+ * advanced by its own workgroups, problems never synchronise with each other.
+ * alpha[p] (device, n_p doubles) and f[p] (device or NULL) receive the
+ * solution; out[p] (host) the result.  Tile shapes come from the built-in
+ * autotuner unless params[p].grid_blocks / lanes_per_row are set. */
+int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* params, double* const* alpha,
+                    double* const* f, svm_result_t* out, void* stream);
+
+/* ---- serving: continuous batching of training problems */
+/* Create a server with a device-memory budget (bytes of solver state it may
+ * keep resident) and at most max_slots problems in flight.  The server owns
+ * one persistent device loop that picks up admitted problems as slots and
+ * memory free up. */
+int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server);
+/* Queue a problem (its arrays must stay valid until the ticket completes).
+ * alpha: n doubles (device) that receive the solution.  Returns a ticket. */
+int svm_server_submit(void* server, const svm_problem_t* prob, const svm_params_t* params, double* alpha,
+                      int64_t* ticket);
+/* SVM_OK and *out filled when done, SVM_EBUSY while queued or running. */
+int svm_server_poll(void* server, int64_t ticket, svm_result_t* out);
+/* Block until every submitted problem has completed. */
+int svm_server_drain(void* server);
+/* Serving counters (host): admitted, deferred-for-memory, completed, in flight. */
+int svm_server_stats(void* server, int64_t* admitted, int64_t* deferred, int64_t* completed, int64_t* in_flight);
+int svm_server_destroy(void* server);
+
+const char* svm_strerror(int code);
+int svm_version(void);
+
+/* ---- test hooks */
+/* Two-threshold selection (eq:bminmax) over the samples listed in `active`
+ * (n_active ids; order irrelevant), from f, alpha and y (device arrays of the
+ * full problem) and C, with the same block/grid reduction as the training
+ * loop split over `num_blocks` workgroups (0 = automatic).  Ties go to the
+ * lowest sample id; an empty side yields +-inf and id -1.  Outputs are host. */
+int svm_debug_select(int32_t n_active, const int32_t* active, const double* f, const double* alpha,
+                     const int8_t* y, double C, int32_t num_blocks, double* b_up, int32_t* i_up, double* b_low,
+                     int32_t* i_low, void* stream);
+
+/* Per-iteration pair trace of the next svm_train call on this host thread:
+ * up to `cap` records of (i_up, i_low) and (b_up, b_low) as selected before
+ * each pair update (device arrays).  Pass cap = 0 to switch it off. */
+int svm_debug_set_trace(int64_t cap, int32_t* i_up, int32_t* i_low, double* b_up, double* b_low);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVMHIP_H */
