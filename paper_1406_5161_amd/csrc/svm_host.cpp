@@ -1,0 +1,601 @@
+// svm_host.cpp -- host side of libsvmhip.so: argument checks, workspace plan,
+// the phase driver of Alg. 5 (and its multi-reconstruction variant), gradient
+// reconstruction (Alg. 6), the classifier of eq:classi and the test hooks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "svm_internal.h"
+
+using namespace svm;
+
+namespace {
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) {                        \
+            last_hip_error() = _e;                     \
+            return SVM_EHIP;                           \
+        }                                              \
+    } while (0)
+
+hipError_t& last_hip_error() {
+    static thread_local hipError_t e = hipSuccess;
+    return e;
+}
+
+struct TraceCfg {
+    int64_t cap = 0;
+    int32_t* iu = nullptr;
+    int32_t* il = nullptr;
+    double* bu = nullptr;
+    double* bl = nullptr;
+};
+TraceCfg& trace_cfg() {
+    static thread_local TraceCfg t;
+    return t;
+}
+
+constexpr int NSPLIT_MAX = 16;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Plan {
+    size_t ctl, xpack, fint, status, mask, act, seg, cnt, rec, listw, listz, coef, blkcnt, counts, part, sumblk,
+        out6, total;
+};
+
+int dpad_of(int d) { return (d + 3) & ~3; }
+
+Plan make_plan(const svm_problem_t* p) {
+    const size_t n = (size_t)p->n;
+    Plan q{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    q.ctl = take(CTL_BYTES);
+    q.xpack = take(p->layout == SVM_CSR ? 0 : sizeof(float) * n * (size_t)dpad_of(p->d));
+    q.fint = take(sizeof(double) * n);
+    q.status = take(n);
+    q.mask = take(n);
+    q.act = take(sizeof(int32_t) * n);
+    q.seg = take(sizeof(int32_t) * (MAX_GRID + 1));
+    q.cnt = take(sizeof(int32_t) * MAX_GRID);
+    q.rec = take(sizeof(Rec) * 2 * MAX_GRID);
+    q.listw = take(sizeof(int32_t) * n);
+    q.listz = take(sizeof(int32_t) * n);
+    q.coef = take(sizeof(double) * n);
+    q.blkcnt = take(sizeof(int32_t) * (n / 1024 + 4));
+    q.counts = take(64);
+    q.part = take(sizeof(double) * n * NSPLIT_MAX);
+    q.sumblk = take(sizeof(double) * 256 * 6);
+    q.out6 = take(64);
+    q.total = o;
+    return q;
+}
+
+int check_problem(const svm_problem_t* p, bool need_labels) {
+    if (!p || p->n < 1 || p->d < 1) return SVM_EINVAL;
+    if (need_labels && (!p->y || p->n < 2)) return SVM_EINVAL;
+    if (p->layout == SVM_CSR) {
+        if (!p->row_ptr || !p->col || !p->val) return SVM_EINVAL;
+        if (p->d > SLOT_MAX_D) return SVM_EUNSUPPORTED;
+    } else if (p->layout == SVM_DENSE_ROW_MAJOR) {
+        if (!p->x || p->ldx < p->d) return SVM_EINVAL;
+    } else if (p->layout == SVM_DENSE_FEATURE_MAJOR) {
+        if (!p->x || p->ldx < p->n) return SVM_EINVAL;
+    } else {
+        return SVM_EINVAL;
+    }
+    return SVM_OK;
+}
+
+int check_params(const svm_params_t* q) {
+    if (!q) return SVM_EINVAL;
+    if (!(q->C > 0) || !(q->gamma > 0) || !(q->eps > 0) || !std::isfinite(q->C) || !std::isfinite(q->gamma) ||
+        !std::isfinite(q->eps))
+        return SVM_EINVAL;
+    if (q->shrink_mode < 0 || q->shrink_mode > 2) return SVM_EINVAL;
+    if (q->shrink_mode != SVM_SHRINK_NONE && !(q->shrink_param > 0)) return SVM_EINVAL;
+    if (q->shrink_kind < 0 || q->shrink_kind > 1) return SVM_EINVAL;
+    if (q->max_iter <= 0) return SVM_EINVAL;
+    if (q->kernel_precision != SVM_KERNEL_FP32 && q->kernel_precision != SVM_KERNEL_FP64) return SVM_EINVAL;
+    if (q->grid_blocks < 0 || q->grid_blocks > MAX_GRID) return SVM_EINVAL;
+    int l = q->lanes_per_row;
+    if (l < 0 || l > 64 || (l & (l - 1))) return SVM_EINVAL;
+    return SVM_OK;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Everything one training call needs on the device.
+struct Solver {
+    const svm_problem_t* p;
+    const svm_params_t* q;
+    hipStream_t s;
+    unsigned char* ws;
+    Plan plan;
+    int n, d, dpad, lay, G, lpr;
+    bool pattern_only;
+    int max_row_nnz;
+    double* alpha;
+    double* f;
+    Ctl* ctl;
+    unsigned long long* bar;
+    uint8_t* status;
+    uint8_t* mask;
+    int32_t* act;
+    int32_t* seg;
+    int32_t* cnt;
+    Rec* rec;
+    int32_t* listw;
+    int32_t* listz;
+    double* coef;
+    int32_t* blkcnt;
+    int32_t* counts;
+    double* part;
+    double* sumblk;
+    double* out6;
+    const float* xin;      // dense values the kernels read (packed)
+    Ctl h{};                // host mirror of ctl
+    double ms_step = 0, ms_recon = 0;
+    int n_launch = 0;
+
+    template <typename T>
+    T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+
+    int read_ctl() {
+        HIP_TRY(hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return SVM_OK;
+    }
+    int write_ctl() {
+        HIP_TRY(hipMemcpyAsync(ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, s));
+        return SVM_OK;
+    }
+
+    int select_all() {
+        HIP_TRY(launch_select(G, seg, cnt, act, f, alpha, p->y, q->C, rec, ctl, s));
+        return read_ctl();
+    }
+
+    // f of the rows in `rows` (count from counts[0] or `nrows`) from the support vectors (Alg. 6).
+    int kernel_sum_rows(const int32_t* rows, int nrows) {
+        if (nrows <= 0) return SVM_OK;
+        // support vectors: ascending ids with alpha > 0, coefficient alpha * y
+        HIP_TRY(launch_compact(n, 1, mask, alpha, p->y, blkcnt, listz, coef, counts + 1, s));
+        int32_t nz = 0;
+        HIP_TRY(hipMemcpyAsync(&nz, counts + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        SumArgs a{};
+        a.lay = lay == LAY_DENSE ? LAY_DENSE : LAY_CSR_TABLE;
+        a.d = d;
+        a.dpad = dpad;
+        a.ax = a.bx = xin;
+        a.arp = a.brp = p->row_ptr;
+        a.acol = a.bcol = p->col;
+        a.aval = a.bval = p->val;
+        a.alist = rows;
+        a.na = nrows;
+        a.blist = listz;
+        a.coef = coef;
+        a.nb = nz;
+        a.gamma = q->gamma;
+        const int W = lay == LAY_DENSE ? dpad : d;
+        int R = (int)std::min<size_t>(16, (96 * 1024) / (sizeof(float) * (size_t)W));
+        if (R < 1) return SVM_EUNSUPPORTED;
+        a.rows_per_block = R;
+        const int blocks = (nrows + R - 1) / R;
+        int ns = std::max(1, std::min(NSPLIT_MAX, (2048 + blocks - 1) / blocks));
+        ns = std::min(ns, std::max(1, nz / 256));
+        a.nsplit = ns;
+        a.part = part;
+        HIP_TRY(launch_kernel_sum(a, q->kernel_precision, s));
+        HIP_TRY(launch_finish_sum(nrows, ns, part, rows, p->y, 0.0, f, s));
+        return SVM_OK;
+    }
+
+    int reconstruct_shrunk() {
+        double t0 = now_ms();
+        HIP_TRY(launch_mark_active(n, G, seg, cnt, act, mask, s));
+        HIP_TRY(launch_compact(n, 0, mask, alpha, p->y, blkcnt, listw, nullptr, counts, s));
+        int32_t nw = 0;
+        HIP_TRY(hipMemcpyAsync(&nw, counts, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int rc = kernel_sum_rows(listw, nw);
+        if (rc) return rc;
+        HIP_TRY(launch_reset_active(n, G, seg, cnt, act, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        ms_recon += now_ms() - t0;
+        return SVM_OK;
+    }
+
+    int recompute_all() {
+        double t0 = now_ms();
+        int rc = kernel_sum_rows(nullptr, n);
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(s));
+        ms_recon += now_ms() - t0;
+        return SVM_OK;
+    }
+
+    int run_loop(double thr, int64_t H) {
+        StepArgs a{};
+        a.n = n; a.d = d; a.dpad = dpad; a.lay = lay;
+        a.x = xin;
+        a.row_ptr = p->row_ptr; a.col = p->col; a.val = p->val;
+        a.pattern_only = pattern_only ? 1 : 0;
+        a.max_row_nnz = max_row_nnz;
+        a.y = p->y;
+        a.alpha = alpha; a.f = f; a.status = status;
+        a.act = act; a.seg_start = seg; a.cnt = cnt;
+        a.rec = rec; a.ctl = ctl; a.bar = bar;
+        a.C = q->C; a.gamma = q->gamma; a.thr = thr;
+        a.max_iter = q->max_iter;
+        a.H = H;
+        TraceCfg& t = trace_cfg();
+        a.trace_cap = t.cap; a.tr_iu = t.iu; a.tr_il = t.il; a.tr_bu = t.bu; a.tr_bl = t.bl;
+        a.spin_limit = 500ull * 1000 * 1000;   // 5 s of the 100 MHz wall clock per barrier wait
+        HIP_TRY(hipMemsetAsync(bar, 0, sizeof(unsigned long long), s));
+        double t0 = now_ms();
+        HIP_TRY(launch_step(a, G, lpr, q->kernel_precision, s));
+        int rc = read_ctl();
+        ms_step += now_ms() - t0;
+        ++n_launch;
+        return rc;
+    }
+};
+
+int64_t heuristic_h(const svm_params_t* q, int n) {
+    double h = q->shrink_kind == SVM_KIND_FIXED ? q->shrink_param : std::ceil(q->shrink_param * (double)n);
+    if (h < 1) h = 1;
+    return (int64_t)h;
+}
+
+int choose_lpr(const svm_problem_t* p, const svm_params_t* q) {
+    if (p->layout != SVM_CSR) return 1;
+    if (q->lanes_per_row) return q->lanes_per_row;
+    return -1;  // filled once nnz is known
+}
+
+int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, double* f_out, svm_result_t* out,
+               void* workspace, size_t ws_bytes, hipStream_t s) {
+    const double t_start = now_ms();
+    Solver S{};
+    S.p = p; S.q = q; S.s = s;
+    S.plan = make_plan(p);
+    if (ws_bytes < S.plan.total || ((uintptr_t)workspace & (ALIGN - 1))) return SVM_EWORKSPACE;
+    S.ws = (unsigned char*)workspace;
+    S.n = p->n; S.d = p->d; S.dpad = dpad_of(p->d);
+    S.alpha = alpha;
+    S.f = f_out ? f_out : S.at<double>(S.plan.fint);
+    S.ctl = S.at<Ctl>(S.plan.ctl);
+    S.bar = S.at<unsigned long long>(S.plan.ctl + 256);
+    S.status = S.at<uint8_t>(S.plan.status);
+    S.mask = S.at<uint8_t>(S.plan.mask);
+    S.act = S.at<int32_t>(S.plan.act);
+    S.seg = S.at<int32_t>(S.plan.seg);
+    S.cnt = S.at<int32_t>(S.plan.cnt);
+    S.rec = S.at<Rec>(S.plan.rec);
+    S.listw = S.at<int32_t>(S.plan.listw);
+    S.listz = S.at<int32_t>(S.plan.listz);
+    S.coef = S.at<double>(S.plan.coef);
+    S.blkcnt = S.at<int32_t>(S.plan.blkcnt);
+    S.counts = S.at<int32_t>(S.plan.counts);
+    S.part = S.at<double>(S.plan.part);
+    S.sumblk = S.at<double>(S.plan.sumblk);
+    S.out6 = S.at<double>(S.plan.out6);
+
+    // ---- validate on the device
+    HIP_TRY(hipMemsetAsync(S.ctl, 0, CTL_BYTES, s));
+    HIP_TRY(launch_validate(p->n, p->d, p->layout, p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR, p->row_ptr,
+                            p->col, p->val, p->y, S.ctl, s));
+    int rc = S.read_ctl();
+    if (rc) return rc;
+    if (S.h.err & 1) return SVM_EINVAL;
+    if (S.h.err & 2) return SVM_ENONFINITE;
+    if (S.h.n_pos == 0 || S.h.n_neg == 0) return SVM_EONECLASS;
+
+    if (p->layout == SVM_CSR) {
+        S.max_row_nnz = S.h.max_row_nnz;
+        int32_t nnz = 0;
+        HIP_TRY(hipMemcpyAsync(&nnz, p->row_ptr + p->n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(launch_check_pattern(0, nullptr, S.counts + 2, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(launch_check_pattern(nnz, p->val, S.counts + 2, s));
+        int32_t notpat = 1;
+        HIP_TRY(hipMemcpyAsync(&notpat, S.counts + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        S.pattern_only = notpat == 0;
+        S.lay = p->d <= TABLE_MAX_D ? LAY_CSR_TABLE : LAY_CSR_SLOT;
+        if (S.lay == LAY_CSR_SLOT && S.max_row_nnz > SLOT_MAX_NNZ) return SVM_EUNSUPPORTED;
+        S.lpr = choose_lpr(p, q);
+        if (S.lpr < 0) {
+            double avg = (double)nnz / (double)p->n;
+            int l = 1;
+            while (l < 32 && 4 * l * 2 <= avg) l *= 2;
+            S.lpr = l;
+        }
+        S.xin = nullptr;
+    } else {
+        S.lay = LAY_DENSE;
+        S.lpr = 1;
+        S.max_row_nnz = 0;
+        float* xp = S.at<float>(S.plan.xpack);
+        HIP_TRY(launch_pack_dense(p->n, p->d, S.dpad, p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR, xp, s));
+        S.xin = xp;
+    }
+
+    // ---- grid size: co-resident workgroups (cooperative launch), about 1024 rows each
+    const size_t lds = step_lds_bytes(S.lay, S.d, S.dpad, S.max_row_nnz);
+    if (lds > 160 * 1024) return SVM_EUNSUPPORTED;
+    int maxG = std::min(MAX_GRID, step_max_blocks(S.lay, S.lpr, q->kernel_precision, lds));
+    if (maxG < 1) return SVM_EUNSUPPORTED;
+    int G = q->grid_blocks ? q->grid_blocks : std::max(1, (p->n + 1023) / 1024);
+    G = std::min(G, maxG);
+    G = std::min(G, p->n);
+    S.G = G;
+
+    // ---- initial state: alpha = 0, f = -y (or the caller's warm start), everything active
+    const bool warm = (q->flags & SVM_FLAG_WARM_START) != 0;
+    if (warm && !f_out) return SVM_EINVAL;
+    HIP_TRY(launch_init_state(p->n, p->y, q->C, warm ? 1 : 0, alpha, S.f, S.status, s));
+    HIP_TRY(launch_reset_active(p->n, G, S.seg, S.cnt, S.act, s));
+    rc = S.select_all();
+    if (rc) return rc;
+
+    const double eps = q->eps;
+    bool shrinking = q->shrink_mode != SVM_SHRINK_NONE;
+    const int64_t H = shrinking ? heuristic_h(q, p->n) : 0;
+    double thr = shrinking ? 20.0 * eps : 2.0 * eps;
+    S.h.iter = 0;
+    S.h.counter = H;
+    S.h.shrink_passes = 0;
+    S.h.shrunk_total = 0;
+    S.h.abort = 0;
+    S.h.exit_reason = 0;
+    if ((rc = S.write_ctl())) return rc;
+
+    int status = SVM_OK;
+    int n_recon = 0;
+    int rechecks = 0;
+    const bool final_recompute = q->kernel_precision == SVM_KERNEL_FP32 && !(q->flags & SVM_FLAG_NO_FINAL_RECOMPUTE);
+    for (;;) {
+        if ((rc = S.run_loop(thr, shrinking ? H : 0))) return rc;
+        if (S.h.exit_reason == EXIT_ABORT) return SVM_EABORT;
+        if (S.h.exit_reason == EXIT_MAXITER) { status = SVM_NOT_CONVERGED; break; }
+        if (shrinking) {
+            // the active set meets the tolerance: rebuild f of the shrunk samples (Alg. 6)
+            if ((rc = S.reconstruct_shrunk())) return rc;
+            ++n_recon;
+            Ctl keep = S.h;
+            if ((rc = S.select_all())) return rc;
+            S.h.iter = keep.iter; S.h.shrink_passes = keep.shrink_passes; S.h.shrunk_total = keep.shrunk_total;
+            S.h.counter = H;
+            if (S.h.b_low - S.h.b_up > 2.0 * eps) {
+                thr = 2.0 * eps;
+                if (q->shrink_mode == SVM_SHRINK_SINGLE) shrinking = false;
+                if ((rc = S.write_ctl())) return rc;
+                continue;
+            }
+            if ((rc = S.write_ctl())) return rc;
+        }
+        if (final_recompute && rechecks < 2) {
+            // closing FP64-accumulated recompute of f from alpha (removes FP32 drift), then re-test
+            ++rechecks;
+            if ((rc = S.recompute_all())) return rc;
+            Ctl keep = S.h;
+            if ((rc = S.select_all())) return rc;
+            S.h.iter = keep.iter; S.h.shrink_passes = keep.shrink_passes; S.h.shrunk_total = keep.shrunk_total;
+            S.h.counter = H;
+            if ((rc = S.write_ctl())) return rc;
+            if (S.h.b_low - S.h.b_up > 2.0 * eps) {
+                thr = 2.0 * eps;
+                continue;
+            }
+        }
+        break;
+    }
+    if (status == SVM_NOT_CONVERGED && S.h.n_active < p->n) {
+        if ((rc = S.reconstruct_shrunk())) return rc;
+        ++n_recon;
+        Ctl keep = S.h;
+        if ((rc = S.select_all())) return rc;
+        S.h.iter = keep.iter; S.h.shrink_passes = keep.shrink_passes; S.h.shrunk_total = keep.shrunk_total;
+    }
+
+    // ---- threshold and summary
+    HIP_TRY(launch_summary(p->n, alpha, S.f, p->y, q->C, S.sumblk, S.out6, s));
+    double v6[6];
+    HIP_TRY(hipMemcpyAsync(v6, S.out6, sizeof(v6), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (out) {
+        memset(out, 0, sizeof(*out));
+        out->beta = v6[1] > 0 ? v6[0] / v6[1] : 0.5 * (S.h.b_up + S.h.b_low);
+        out->b_up = S.h.b_up;
+        out->b_low = S.h.b_low;
+        out->dual_obj = v6[2] - 0.5 * v6[3];
+        out->iterations = S.h.iter;
+        out->n_sv = (int32_t)v6[4];
+        out->n_bsv = (int32_t)v6[5];
+        out->n_recon = n_recon;
+        out->status = status;
+        out->shrink_passes = S.h.shrink_passes;
+        out->shrunk_total = S.h.shrunk_total;
+        out->n_launches = S.n_launch;
+        out->grid_blocks = S.G;
+        out->ms_total = now_ms() - t_start;
+        out->ms_step = S.ms_step;
+        out->ms_recon = S.ms_recon;
+    }
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t svm_train_workspace_size(const svm_problem_t* prob, const svm_params_t* params) {
+    if (check_problem(prob, true) || check_params(params)) return 0;
+    return make_plan(prob).total;
+}
+
+int svm_train(const svm_problem_t* prob, const svm_params_t* params, double* alpha, double* f, svm_result_t* out,
+              void* workspace, size_t ws_bytes, void* stream) {
+    int rc = check_problem(prob, true);
+    if (rc) return rc;
+    if ((rc = check_params(params))) return rc;
+    if (!alpha) return SVM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    void* own = nullptr;
+    if (!workspace) {
+        ws_bytes = make_plan(prob).total;
+        if (hipMalloc(&own, ws_bytes) != hipSuccess) return SVM_ENOMEM;
+        workspace = own;
+    }
+    rc = train_impl(prob, params, alpha, f, out, workspace, ws_bytes, s);
+    if (own) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(own);
+    }
+    return rc;
+}
+
+int svm_decision(const svm_problem_t* train, const double* alpha, double beta, double gamma,
+                 const svm_problem_t* queries, double* out, int32_t kernel_precision, void* stream) {
+    int rc = check_problem(train, true);
+    if (rc) return rc;
+    if ((rc = check_problem(queries, false))) return rc;
+    if (!alpha || !out || !(gamma > 0) || queries->d != train->d) return SVM_EINVAL;
+    if ((train->layout == SVM_CSR) != (queries->layout == SVM_CSR)) return SVM_EINVAL;
+    if (kernel_precision != SVM_KERNEL_FP32 && kernel_precision != SVM_KERNEL_FP64) return SVM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = train->n, nq = queries->n, d = train->d, dpad = dpad_of(d);
+    const bool dense = train->layout != SVM_CSR;
+    if (!dense && d > 40960) return SVM_EUNSUPPORTED;
+    // scratch: packed train + queries (dense), SV list + coefficients, partial sums
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t a = o; o = align_up(o + b); return a; };
+    const size_t o_xt = take(dense ? sizeof(float) * (size_t)n * dpad : 0);
+    const size_t o_xq = take(dense ? sizeof(float) * (size_t)nq * dpad : 0);
+    const size_t o_lz = take(sizeof(int32_t) * (size_t)n);
+    const size_t o_cf = take(sizeof(double) * (size_t)n);
+    const size_t o_bc = take(sizeof(int32_t) * ((size_t)n / 1024 + 4));
+    const size_t o_ct = take(64);
+    const size_t o_pt = take(sizeof(double) * (size_t)nq * NSPLIT_MAX);
+    unsigned char* buf = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&buf, o, s));
+    auto cleanup = [&]() { (void)hipFreeAsync(buf, s); (void)hipStreamSynchronize(s); };
+    float* xt = (float*)(buf + o_xt);
+    float* xq = (float*)(buf + o_xq);
+    int32_t* lz = (int32_t*)(buf + o_lz);
+    double* cf = (double*)(buf + o_cf);
+    int32_t* bc = (int32_t*)(buf + o_bc);
+    int32_t* ct = (int32_t*)(buf + o_ct);
+    double* pt = (double*)(buf + o_pt);
+    hipError_t e = hipSuccess;
+    if (dense) {
+        e = launch_pack_dense(n, d, dpad, train->x, train->ldx, train->layout == SVM_DENSE_FEATURE_MAJOR, xt, s);
+        if (e == hipSuccess)
+            e = launch_pack_dense(nq, d, dpad, queries->x, queries->ldx, queries->layout == SVM_DENSE_FEATURE_MAJOR,
+                                  xq, s);
+    }
+    if (e == hipSuccess) e = launch_compact(n, 1, nullptr, alpha, train->y, bc, lz, cf, ct, s);
+    int32_t cnts[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(cnts, ct, sizeof(cnts), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { last_hip_error() = e; cleanup(); return SVM_EHIP; }
+    SumArgs a{};
+    a.lay = dense ? LAY_DENSE : LAY_CSR_TABLE;
+    a.d = d; a.dpad = dpad;
+    a.ax = xq; a.arp = queries->row_ptr; a.acol = queries->col; a.aval = queries->val;
+    a.alist = nullptr; a.na = nq;
+    a.bx = xt; a.brp = train->row_ptr; a.bcol = train->col; a.bval = train->val;
+    a.blist = lz; a.coef = cf; a.nb = cnts[0];
+    a.gamma = gamma;
+    const int W = dense ? dpad : d;
+    int R = (int)std::min<size_t>(16, (96 * 1024) / (sizeof(float) * (size_t)W));
+    if (R < 1) R = 1;
+    a.rows_per_block = R;
+    const int blocks = (nq + R - 1) / R;
+    int ns = std::max(1, std::min(NSPLIT_MAX, (2048 + blocks - 1) / blocks));
+    ns = std::min(ns, std::max(1, cnts[0] / 256));
+    a.nsplit = ns;
+    a.part = pt;
+    e = launch_kernel_sum(a, kernel_precision, s);
+    if (e == hipSuccess) e = launch_finish_sum(nq, ns, pt, nullptr, nullptr, beta, out, s);
+    if (e != hipSuccess) { last_hip_error() = e; cleanup(); return SVM_EHIP; }
+    cleanup();
+    return SVM_OK;
+}
+
+int svm_debug_select(int32_t n_active, const int32_t* active, const double* f, const double* alpha, const int8_t* y,
+                     double C, int32_t num_blocks, double* b_up, int32_t* i_up, double* b_low, int32_t* i_low,
+                     void* stream) {
+    if (n_active < 0 || !active || !f || !alpha || !y || !(C > 0) || num_blocks < 0 || num_blocks > MAX_GRID)
+        return SVM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int G = num_blocks ? num_blocks : std::max(1, std::min(MAX_GRID, (n_active + 1023) / 1024));
+    std::vector<int32_t> seg(G + 1), cnt(G);
+    for (int b = 0; b <= G; ++b) seg[b] = (int32_t)(((int64_t)n_active * b) / G);
+    for (int b = 0; b < G; ++b) cnt[b] = seg[b + 1] - seg[b];
+    size_t bytes = align_up(sizeof(Ctl)) + align_up(sizeof(Rec) * G) + align_up(sizeof(int32_t) * (2 * G + 1));
+    unsigned char* buf = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&buf, bytes, s));
+    Ctl* ctl = (Ctl*)buf;
+    Rec* rec = (Rec*)(buf + align_up(sizeof(Ctl)));
+    int32_t* dseg = (int32_t*)(buf + align_up(sizeof(Ctl)) + align_up(sizeof(Rec) * G));
+    int32_t* dcnt = dseg + G + 1;
+    hipError_t e = hipMemcpyAsync(dseg, seg.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dcnt, cnt.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_select(G, dseg, dcnt, active, f, alpha, y, C, rec, ctl, s);
+    Ctl h{};
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(buf, s);
+    (void)hipStreamSynchronize(s);
+    if (e != hipSuccess) { last_hip_error() = e; return SVM_EHIP; }
+    *b_up = h.b_up; *i_up = h.i_up; *b_low = h.b_low; *i_low = h.i_low;
+    return SVM_OK;
+}
+
+int svm_debug_set_trace(int64_t cap, int32_t* i_up, int32_t* i_low, double* b_up, double* b_low) {
+    if (cap < 0 || (cap > 0 && (!i_up || !i_low || !b_up || !b_low))) return SVM_EINVAL;
+    TraceCfg& t = trace_cfg();
+    t.cap = cap; t.iu = i_up; t.il = i_low; t.bu = b_up; t.bl = b_low;
+    return SVM_OK;
+}
+
+const char* svm_strerror(int code) {
+    switch (code) {
+        case SVM_OK: return "ok";
+        case SVM_NOT_CONVERGED: return "iteration cap reached before the KKT tolerance (state is consistent)";
+        case SVM_EINVAL: return "invalid argument (sizes, C/gamma/eps, labels or CSR structure)";
+        case SVM_EONECLASS: return "only one class present in the labels";
+        case SVM_ENONFINITE: return "NaN or Inf in the sample values";
+        case SVM_EWORKSPACE: return "workspace too small or not 256-byte aligned";
+        case SVM_EHIP: return hipGetErrorString(last_hip_error());
+        case SVM_EUNSUPPORTED: return "problem shape not supported by this build";
+        case SVM_ENOMEM: return "device allocation failed or memory budget exhausted";
+        case SVM_EBUSY: return "ticket still queued or running";
+        case SVM_EABORT: return "device loop stopped by its barrier watchdog";
+        default: return "unknown status code";
+    }
+}
+
+int svm_version(void) { return 100; }
+
+}  // extern "C"

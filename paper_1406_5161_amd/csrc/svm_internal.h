@@ -1,0 +1,141 @@
+// svm_internal.h -- types shared by the device kernels and the host driver of
+// libsvmhip.so.  Not part of the public C-ABI (include/svmhip.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "svmhip.h"
+
+namespace svm {
+
+// sample layouts inside the library
+enum : int { LAY_DENSE = 0, LAY_CSR_TABLE = 1, LAY_CSR_SLOT = 2 };
+
+// why a persistent-loop launch returned
+enum : int { EXIT_NONE = 0, EXIT_CONVERGED = 1, EXIT_MAXITER = 2, EXIT_ABORT = 3 };
+
+constexpr int STEP_BLOCK = 1024;      // threads per workgroup of the persistent step
+constexpr int TABLE_MAX_D = 12288;    // CSR: dense float2 pair table in LDS up to this d (96 KB)
+constexpr int SLOT_MAX_D = 65536;     // CSR: u16 slot map in LDS up to this d
+constexpr int SLOT_MAX_NNZ = 2048;    // CSR slot map: longest row
+constexpr int MAX_GRID = 1024;        // records are reduced by one workgroup
+constexpr int CTL_BYTES = 512;
+
+// Status byte of a sample: bit 0 = label is +1; bits 1-2 = bound class
+// (0: alpha == 0, 1: 0 < alpha < C, 2: alpha == C).
+enum : uint8_t { ST_YPOS = 1, ST_FREE = 2, ST_ATC = 4 };
+
+// Selection state and counters of the solver, kept in device memory between
+// launches of the persistent loop.
+struct Ctl {
+    double b_up, b_low;
+    int32_t i_up, i_low;
+    int64_t iter;
+    int64_t counter;          // iterations left until the next shrink pass
+    int64_t n_active;
+    int64_t shrink_passes;
+    int64_t shrunk_total;
+    int32_t exit_reason;
+    int32_t abort;
+    int32_t err;              // validation error bits
+    int32_t n_pos, n_neg;
+    int32_t max_row_nnz;
+    int32_t pad[4];
+};
+static_assert(sizeof(Ctl) <= 256, "Ctl must fit in its slot");
+
+// One workgroup's partial selection: (b_up bits, b_low bits, i_up | i_low << 32, active count).
+struct Rec {
+    unsigned long long w[4];
+};
+
+struct StepArgs {
+    int32_t n, d, dpad, lay;
+    const float* x;           // dense: internal row-major [n][dpad]
+    const int32_t* row_ptr;   // csr
+    const int32_t* col;
+    const float* val;
+    int32_t pattern_only;     // csr values all 1.0: skip reading val
+    int32_t max_row_nnz;
+    const int8_t* y;
+    double* alpha;
+    double* f;
+    uint8_t* status;
+    int32_t* act;             // active ids, segmented by workgroup
+    const int32_t* seg_start; // [G+1]
+    int32_t* cnt;             // [G] active count of each segment
+    Rec* rec;                 // [2*G] partial selections, double-buffered by iteration parity
+    Ctl* ctl;
+    unsigned long long* bar;  // grid-barrier counter, zeroed before each launch
+    double C, gamma, thr;
+    int64_t max_iter;
+    int64_t H;                // shrink schedule value (0: no shrinking in this launch)
+    int64_t trace_cap;
+    int32_t* tr_iu;
+    int32_t* tr_il;
+    double* tr_bu;
+    double* tr_bl;
+    unsigned long long spin_limit;  // watchdog for one barrier wait (wall-clock ticks)
+};
+
+// Kernel sums: out[a] = sum_b coef[b] * K(A_a, B_b) + bias_a, bias_a = -y_a or -beta.
+struct SumArgs {
+    int32_t lay;              // LAY_DENSE or LAY_CSR_TABLE (A and B share the layout)
+    int32_t d, dpad;
+    // A side
+    const float* ax;
+    const int32_t* arp;
+    const int32_t* acol;
+    const float* aval;
+    const int32_t* alist;     // rows of A to evaluate (na)
+    int32_t na;
+    // B side
+    const float* bx;
+    const int32_t* brp;
+    const int32_t* bcol;
+    const float* bval;
+    const int32_t* blist;     // rows of B in the sum (nb), ascending
+    const double* coef;       // [nb]
+    int32_t nb;
+    int32_t nsplit;           // B split across blockIdx.y; partial sums in part[split][a]
+    double* part;
+    double gamma;
+    int32_t rows_per_block;   // A rows held in LDS per workgroup
+};
+
+// ---- launch wrappers (device code in svm_kernels.hip)
+hipError_t launch_validate(int n, int d, int lay, const float* x, int64_t ldx, int feature_major,
+                           const int32_t* rp, const int32_t* col, const float* val, const int8_t* y, Ctl* ctl,
+                           hipStream_t s);
+hipError_t launch_pack_dense(int n, int d, int dpad, const float* x, int64_t ldx, int feature_major, float* out,
+                             hipStream_t s);
+hipError_t launch_init_state(int n, const int8_t* y, double C, int warm, double* alpha, double* f, uint8_t* status,
+                             hipStream_t s);
+hipError_t launch_reset_active(int n, int G, int32_t* seg_start, int32_t* cnt, int32_t* act, hipStream_t s);
+hipError_t launch_select(int G, const int32_t* seg_start, const int32_t* cnt, const int32_t* act, const double* f,
+                         const double* alpha, const int8_t* y, double C, Rec* rec, Ctl* ctl, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, hipStream_t s);
+size_t step_lds_bytes(int lay, int d, int dpad, int max_row_nnz);
+int step_max_blocks(int lay, int lpr, int kprec, size_t lds);
+hipError_t launch_mark_active(int n, int G, const int32_t* seg_start, const int32_t* cnt, const int32_t* act,
+                              uint8_t* mask, hipStream_t s);
+// stable compaction: list = ascending ids i with pred(i); pred: 0 = mask[i]==0, 1 = alpha[i] > 0, 2 = all
+hipError_t launch_compact(int n, int pred, const uint8_t* mask, const double* alpha, const int8_t* y,
+                          int32_t* blk_cnt, int32_t* list, double* coef, int32_t* count_out, hipStream_t s);
+hipError_t launch_kernel_sum(const SumArgs& a, int kprec, hipStream_t s);
+// out[alist[r]] = sum_s part[s][r] + bias (bias: -y[alist[r]] if y != NULL, else -beta)
+hipError_t launch_finish_sum(int na, int nsplit, const double* part, const int32_t* alist, const int8_t* y,
+                             double beta, double* out, hipStream_t s);
+hipError_t launch_refresh_status(int n, const double* alpha, const int8_t* y, double C, uint8_t* status,
+                                 hipStream_t s);
+// final scalars: [0] sum f over I0, [1] |I0|, [2] sum alpha, [3] sum alpha y (f + y), [4] n_sv, [5] n_bsv
+hipError_t launch_summary(int n, const double* alpha, const double* f, const int8_t* y, double C, double* blk,
+                          double* out6, hipStream_t s);
+hipError_t launch_csr_row_norm_max(int n, const int32_t* rp, Ctl* ctl, hipStream_t s);
+hipError_t launch_check_pattern(int nnz, const float* val, int32_t* flag, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace svm
