@@ -113,8 +113,12 @@ typedef struct {
     int32_t n_launches;       /* persistent-loop launches (phases) */
     int32_t grid_blocks;      /* workgroups used by the step */
     double ms_total;          /* wall time of the call (host clock) */
-    double ms_step;           /* time in the persistent SMO loop */
-    double ms_recon;          /* time in reconstruction / recompute */
+    double ms_step;           /* time in the persistent SMO loop launches (HIP events on the call's stream) */
+    double ms_recon;          /* time in reconstruction / recompute (host clock) */
+    int64_t rows_streamed;    /* active rows visited by the SMO loop, summed over iterations */
+    int64_t nnz_streamed;     /* CSR: nonzeros of those rows (0 for dense) */
+    int32_t pattern_only;     /* CSR values were all 1.0 and were not read */
+    int32_t lanes_per_row;    /* CSR lanes per row used by the step */
 } svm_result_t;
 
 /* Bytes of device workspace svm_train needs for this problem (256-byte aligned). */

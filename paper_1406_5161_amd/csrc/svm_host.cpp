@@ -49,7 +49,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Plan {
     size_t ctl, xpack, fint, status, mask, act, seg, cnt, rec, listw, listz, coef, blkcnt, counts, part, sumblk,
-        out6, total;
+        out6, work, total;
 };
 
 int dpad_of(int d) { return (d + 3) & ~3; }
@@ -80,6 +80,7 @@ Plan make_plan(const svm_problem_t* p) {
     q.part = take(sizeof(double) * n * NSPLIT_MAX);
     q.sumblk = take(sizeof(double) * 256 * 6);
     q.out6 = take(64);
+    q.work = take(sizeof(unsigned long long) * 2 * MAX_GRID);
     q.total = o;
     return q;
 }
@@ -153,6 +154,13 @@ struct Solver {
     Ctl h{};                // host mirror of ctl
     double ms_step = 0, ms_recon = 0;
     int n_launch = 0;
+    unsigned long long* work = nullptr;
+    unsigned long long rows_streamed = 0, nnz_streamed = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ~Solver() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
 
     template <typename T>
     T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -196,9 +204,16 @@ struct Solver {
         a.gamma = q->gamma;
         const int W = lay == LAY_DENSE ? dpad : d;
         int R = (int)std::min<size_t>(16, (96 * 1024) / (sizeof(float) * (size_t)W));
-        if (R < 1) return SVM_EUNSUPPORTED;
-        a.rows_per_block = R;
-        const int blocks = (nrows + R - 1) / R;
+        int blocks;
+        if (R < 1) {
+            // CSR too wide to stage rows in LDS: slot-map densification, one row per workgroup
+            a.lay = LAY_CSR_SLOT;
+            a.rows_per_block = max_row_nnz;
+            blocks = std::min(nrows, 2048);
+        } else {
+            a.rows_per_block = R;
+            blocks = (nrows + R - 1) / R;
+        }
         int ns = std::max(1, std::min(NSPLIT_MAX, (2048 + blocks - 1) / blocks));
         ns = std::min(ns, std::max(1, nz / 256));
         a.nsplit = ns;
@@ -249,13 +264,21 @@ struct Solver {
         TraceCfg& t = trace_cfg();
         a.trace_cap = t.cap; a.tr_iu = t.iu; a.tr_il = t.il; a.tr_bu = t.bu; a.tr_bl = t.bl;
         a.spin_limit = 500ull * 1000 * 1000;   // 5 s of the 100 MHz wall clock per barrier wait
+        a.work = work;
         HIP_TRY(hipMemsetAsync(bar, 0, sizeof(unsigned long long), s));
-        double t0 = now_ms();
+        HIP_TRY(hipEventRecord(ev0, s));
         HIP_TRY(launch_step(a, G, lpr, q->kernel_precision, s));
+        HIP_TRY(hipEventRecord(ev1, s));
         int rc = read_ctl();
-        ms_step += now_ms() - t0;
+        if (rc) return rc;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+        ms_step += ms;
+        std::vector<unsigned long long> w(2 * (size_t)G);
+        HIP_TRY(hipMemcpy(w.data(), work, sizeof(unsigned long long) * 2 * G, hipMemcpyDeviceToHost));
+        for (int b = 0; b < G; ++b) { rows_streamed += w[2 * b]; nnz_streamed += w[2 * b + 1]; }
         ++n_launch;
-        return rc;
+        return SVM_OK;
     }
 };
 
@@ -298,6 +321,9 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
     S.part = S.at<double>(S.plan.part);
     S.sumblk = S.at<double>(S.plan.sumblk);
     S.out6 = S.at<double>(S.plan.out6);
+    S.work = S.at<unsigned long long>(S.plan.work);
+    HIP_TRY(hipEventCreate(&S.ev0));
+    HIP_TRY(hipEventCreate(&S.ev1));
 
     // ---- validate on the device
     HIP_TRY(hipMemsetAsync(S.ctl, 0, CTL_BYTES, s));
@@ -440,6 +466,10 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
         out->ms_total = now_ms() - t_start;
         out->ms_step = S.ms_step;
         out->ms_recon = S.ms_recon;
+        out->rows_streamed = (int64_t)S.rows_streamed;
+        out->nnz_streamed = (int64_t)S.nnz_streamed;
+        out->pattern_only = S.pattern_only ? 1 : 0;
+        out->lanes_per_row = S.lpr;
     }
     return status;
 }
@@ -485,7 +515,7 @@ int svm_decision(const svm_problem_t* train, const double* alpha, double beta, d
     hipStream_t s = (hipStream_t)stream;
     const int n = train->n, nq = queries->n, d = train->d, dpad = dpad_of(d);
     const bool dense = train->layout != SVM_CSR;
-    if (!dense && d > 40960) return SVM_EUNSUPPORTED;
+    if (!dense && d > SLOT_MAX_D) return SVM_EUNSUPPORTED;
     // scratch: packed train + queries (dense), SV list + coefficients, partial sums
     size_t o = 0;
     auto take = [&](size_t b) { size_t a = o; o = align_up(o + b); return a; };
@@ -528,9 +558,22 @@ int svm_decision(const svm_problem_t* train, const double* alpha, double beta, d
     a.gamma = gamma;
     const int W = dense ? dpad : d;
     int R = (int)std::min<size_t>(16, (96 * 1024) / (sizeof(float) * (size_t)W));
-    if (R < 1) R = 1;
-    a.rows_per_block = R;
-    const int blocks = (nq + R - 1) / R;
+    int blocks;
+    if (R < 1) {
+        // wide CSR queries: slot-map densification needs the longest query row
+        std::vector<int32_t> rp(nq + 1);
+        e = hipMemcpyAsync(rp.data(), queries->row_ptr, sizeof(int32_t) * (nq + 1), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { last_hip_error() = e; cleanup(); return SVM_EHIP; }
+        int mx = 0;
+        for (int i = 0; i < nq; ++i) mx = std::max(mx, rp[i + 1] - rp[i]);
+        a.lay = LAY_CSR_SLOT;
+        a.rows_per_block = mx;
+        blocks = std::min(nq, 2048);
+    } else {
+        a.rows_per_block = R;
+        blocks = (nq + R - 1) / R;
+    }
     int ns = std::max(1, std::min(NSPLIT_MAX, (2048 + blocks - 1) / blocks));
     ns = std::min(ns, std::max(1, cnts[0] / 256));
     a.nsplit = ns;

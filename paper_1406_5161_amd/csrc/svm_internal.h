@@ -78,6 +78,7 @@ struct StepArgs {
     double* tr_bu;
     double* tr_bl;
     unsigned long long spin_limit;  // watchdog for one barrier wait (wall-clock ticks)
+    unsigned long long* work;       // [G][2]: rows and nonzeros streamed by each workgroup in this launch
 };
 
 // Kernel sums: out[a] = sum_b coef[b] * K(A_a, B_b) + bias_a, bias_a = -y_a or -beta.

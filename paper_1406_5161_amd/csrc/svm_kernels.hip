@@ -12,6 +12,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "svm_internal.h"
@@ -258,6 +259,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     int32_t* lst = A.act + seg0;
     int exit_reason = EXIT_NONE;
     unsigned long long bar_target = 0;
+    unsigned long long work_rows = 0, work_nnz = 0;
     __syncthreads();
 
     for (;;) {
@@ -383,6 +385,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         double cbu = INFINITY, cbl = -INFINITY;
         int ciu = IDX_NONE, cil = IDX_NONE;
         int newcount = 0;
+        work_rows += (unsigned long long)nrows;
         for (int base = 0; base < nrows; base += NG) {
             const int t = base + g;
             const bool valid = t < nrows;
@@ -394,6 +397,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     dense_dist<KT>(A.x + (size_t)i * A.dpad, pairv, A.dpad, du2, dl2);
                 } else {
                     const int p0 = A.row_ptr[i], p1 = A.row_ptr[i + 1];
+                    if (gl == 0) work_nnz += (unsigned long long)(p1 - p0);
                     KT nn = 0, su = 0, sl2 = 0;
                     for (int p = p0 + gl; p < p1; p += LPR) {
                         const int c = A.col[p];
@@ -523,6 +527,18 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     }
 
     if (tid == 0) A.cnt[blk] = nrows;
+    if (A.work) {
+        unsigned long long wn = wave_sum(work_nnz);
+        __syncthreads();
+        if (lane == 0) s_v[wid] = __longlong_as_double((long long)wn);
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < NW; ++w) t += (unsigned long long)__double_as_longlong(s_v[w]);
+            A.work[2 * blk] = work_rows;
+            A.work[2 * blk + 1] = t;
+        }
+    }
     if (blk == 0 && tid == 0) {
         ctl->b_up = bu; ctl->b_low = bl; ctl->i_up = iu; ctl->i_low = il;
         ctl->iter = iter; ctl->counter = counter; ctl->n_active = n_act_total;
@@ -1039,8 +1055,87 @@ __global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_kernel(SumArgs A) {
     }
 }
 
+// Large-d CSR: one A row at a time per workgroup, densified through a u16 slot
+// map over the d columns (zeroed once, cleared sparsely after each row).
+template <typename KT>
+__global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_slot_kernel(SumArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double s_red[SUM_BLOCK / 64];
+    __shared__ double s_na;
+    float* av = reinterpret_cast<float*>(smem);                       // [1 + max_row_nnz]
+    uint16_t* slot = reinterpret_cast<uint16_t*>(smem + ((sizeof(float) * (size_t)(1 + A.rows_per_block) + 15) & ~(size_t)15));
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int k = tid; k < A.d; k += SUM_BLOCK) slot[k] = 0;
+    if (tid == 0) av[0] = 0.f;
+    __syncthreads();
+    const KT gam = (KT)A.gamma;
+    const int per = (A.nb + A.nsplit - 1) / A.nsplit;
+    const int b0 = blockIdx.y * per, b1 = min(A.nb, b0 + per);
+    for (int r = blockIdx.x; r < A.na; r += gridDim.x) {
+        const int a = A.alist ? A.alist[r] : r;
+        const int p0 = A.arp[a], p1 = A.arp[a + 1];
+        KT nn = 0;
+        for (int p = p0 + tid; p < p1; p += SUM_BLOCK) {
+            slot[A.acol[p]] = (uint16_t)(1 + p - p0);
+            const float v = A.aval[p];
+            av[1 + p - p0] = v;
+            nn += (KT)v * (KT)v;
+        }
+        nn = wave_sum(nn);
+        if (lane == 0) s_red[wid] = (double)nn;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < SUM_BLOCK / 64; ++w) t += s_red[w];
+            s_na = t;
+        }
+        __syncthreads();
+        const KT na = (KT)s_na;
+        double acc = 0.0;
+        for (int jb = b0 + tid; jb < b1; jb += SUM_BLOCK) {
+            const int j = A.blist[jb];
+            const int q0 = A.brp[j], q1 = A.brp[j + 1];
+            KT nb = 0, dot = 0;
+            for (int q = q0; q < q1; ++q) {
+                const KT v = (KT)A.bval[q];
+                nb += v * v;
+                dot += v * (KT)av[slot[A.bcol[q]]];
+            }
+            KT d2 = na + nb - (KT)2 * dot;
+            if (d2 < (KT)0) d2 = (KT)0;
+            acc += A.coef[jb] * (double)kexp(-gam * d2);
+        }
+        acc = wave_sum(acc);
+        __syncthreads();
+        if (lane == 0) s_red[wid] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < SUM_BLOCK / 64; ++w) t += s_red[w];
+            A.part[(size_t)blockIdx.y * A.na + r] = t;
+        }
+        for (int p = p0 + tid; p < p1; p += SUM_BLOCK) slot[A.acol[p]] = 0;
+        __syncthreads();
+    }
+}
+
 hipError_t launch_kernel_sum(const SumArgs& a, int kprec, hipStream_t s) {
     if (a.na <= 0) return hipSuccess;
+    if (a.lay == LAY_CSR_SLOT) {
+        // rows_per_block carries the longest A row here
+        const size_t lds = ((sizeof(float) * (size_t)(1 + a.rows_per_block) + 15) & ~(size_t)15) +
+                           sizeof(uint16_t) * (size_t)a.d;
+        dim3 grid(std::min(a.na, 2048), a.nsplit);
+        SumArgs c = a;
+        if (kprec == SVM_KERNEL_FP64) {
+            (void)hipFuncSetAttribute((const void*)kernel_sum_slot_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            kernel_sum_slot_kernel<double><<<grid, SUM_BLOCK, lds, s>>>(c);
+        } else {
+            (void)hipFuncSetAttribute((const void*)kernel_sum_slot_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            kernel_sum_slot_kernel<float><<<grid, SUM_BLOCK, lds, s>>>(c);
+        }
+        return hipGetLastError();
+    }
     const int W = a.lay == LAY_DENSE ? a.dpad : a.d;
     const size_t lds = sizeof(float) * (size_t)a.rows_per_block * W;
     dim3 grid((a.na + a.rows_per_block - 1) / a.rows_per_block, a.nsplit);

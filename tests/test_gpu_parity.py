@@ -1,0 +1,355 @@
+"""GPU parity tests: the HIP library (through its C-ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances are the contract's: dual objective relative 1e-6, support-vector set
+identical up to samples within 1e-6 of a bound, decision values absolute 1e-4,
+working-set indices bit-exact.  With FP64 kernel values the library follows the
+oracle's trajectory pair by pair, so every tolerance is checked at every size
+here.  With FP32 kernel values (the fast default) the trajectory is the oracle's
+until FP32 rounding flips a near-tie between two candidates; from there both
+runs reach different, equally valid eps-optimal points.  For those cases the
+tests compare what is unique (the dual objective; the optimum at a tight eps)
+and check that the GPU's own solution is valid (box, equality, KKT on a fresh
+FP64 recompute of f)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1406_5161_amd import datagen as g
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_1406_5161_amd import svmhip
+    svmhip.lib()
+    return svmhip
+
+
+def P(*a):
+    print(*a, flush=True)
+
+
+def gpu_train(S, cfg, prec, trace_cap=0, **kw):
+    import torch
+    tr = None
+    if trace_cap:
+        tr = [torch.zeros(trace_cap, dtype=torch.int32, device="cuda"),
+              torch.zeros(trace_cap, dtype=torch.int32, device="cuda"),
+              torch.zeros(trace_cap, dtype=torch.float64, device="cuda"),
+              torch.zeros(trace_cap, dtype=torch.float64, device="cuda")]
+        S.svm_debug_set_trace(trace_cap, *tr)
+    try:
+        out = S.train_config(cfg, kernel_precision=prec, **kw)
+    finally:
+        S.svm_debug_set_trace(0)
+    trace = None
+    if tr is not None:
+        m = min(out.result["iterations"], trace_cap)
+        trace = {k: v[:m].cpu().numpy() for k, v in zip(["i_up", "i_low", "b_up", "b_low"], tr)}
+    return out, trace
+
+
+def sv_sets_agree(a_gpu, a_ref, C, tol=1e-6):
+    """Support-vector sets identical except samples within tol of a bound on either side."""
+    near = (np.minimum(a_gpu, a_ref) < tol) & (np.maximum(a_gpu, a_ref) > 0)
+    near |= (np.maximum(a_gpu, a_ref) > C - tol) & (np.minimum(a_gpu, a_ref) < C)
+    diff = ((a_gpu > 0) != (a_ref > 0)) | ((a_gpu >= C) != (a_ref >= C))
+    return int(np.sum(diff & ~near))
+
+
+def check_contract(S, cfg, out, ref, prec, nq=2000):
+    r = out.result
+    D_gpu = O.dual(cfg.data, out.alpha, cfg.gamma) if cfg.data.n <= 8000 else r["dual_obj"]
+    D_ref = O.dual(cfg.data, ref.alpha, cfg.gamma) if cfg.data.n <= 8000 else ref.dual_obj
+    rel = abs(D_gpu - D_ref) / abs(D_ref)
+    assert rel <= 1e-6, rel
+    assert sv_sets_agree(out.alpha, ref.alpha, cfg.C) == 0
+    sets = [cfg.data.subset(np.arange(min(nq, cfg.data.n)))]
+    if cfg.queries is not None:
+        sets.append(cfg.queries.subset(np.arange(min(nq, cfg.queries.n))))
+    worst = 0.0
+    for q in sets:
+        dv = S.decision_data(cfg.data, out.alpha, r["beta"], cfg.gamma, q, kernel_precision=prec)
+        dref = O.decision(cfg.data, ref.alpha, ref.beta, cfg.gamma, q)
+        worst = max(worst, float(np.abs(dv - dref).max()))
+    assert worst <= 1e-4, worst
+    return rel, worst
+
+
+def first_divergence(tr, ref_tr):
+    m = min(len(tr["i_up"]), len(ref_tr["i_up"]))
+    bad = np.nonzero((tr["i_up"][:m] != ref_tr["i_up"][:m]) | (tr["i_low"][:m] != ref_tr["i_low"][:m]))[0]
+    return int(bad[0]) if len(bad) else -1
+
+
+def sub(cfg, n, name=None):
+    cfg.data = cfg.data.subset(np.arange(n))
+    cfg.name = name or ("%s_sub%d" % (cfg.name, n))
+    return cfg
+
+
+# ------------------------------------------------------------------ selection (bit-exact)
+
+def select_np(f, a, y, C, S_=None):
+    free = (a > 0) & (a < C)
+    up = free | ((y == 1) & (a == 0)) | ((y == -1) & (a == C))
+    low = free | ((y == 1) & (a == C)) | ((y == -1) & (a == 0))
+    if S_ is not None:
+        m = np.zeros(len(f), bool)
+        m[S_] = True
+        up, low = up & m, low & m
+    fu = np.where(up, f, np.inf)
+    fl = np.where(low, f, -np.inf)
+    iu = int(np.argmin(fu)) if up.any() else -1
+    il = int(np.argmax(fl)) if low.any() else -1
+    return (fu[iu] if iu >= 0 else np.inf), iu, (fl[il] if il >= 0 else -np.inf), il
+
+
+def snapshots():
+    cfg = sub(g.config2(), 2500)
+    out = []
+    for k in (0, 7, 300, 1500):
+        r = O.train_config(cfg, max_iter=k)
+        out.append(("oracle_k%d" % k, r.f, r.alpha, cfg.data.y, cfg.C))
+    rng = np.random.default_rng(5)
+    n, C = 5000, 2.0
+    y = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    a = rng.choice([0.0, C, 0.5, 1.5], size=n)
+    f = np.round(rng.standard_normal(n), 1)
+    out.append(("ties", f, a, y, C))
+    out.append(("all_equal", np.full(n, 0.125), a, y, C))
+    fz = np.where(rng.random(n) < 0.5, -0.0, 0.0)
+    out.append(("signed_zero", fz, a, y, C))
+    ones = np.ones(n, np.int8)
+    out.append(("empty_up", f, np.full(n, C), ones, C))
+    out.append(("single_candidate", f, np.where(np.arange(n) == 4321, 0.5, C), ones, C))
+    fd = np.full(n, 5e-324)
+    fd[::7] = 0.0
+    out.append(("denormals", fd, a, y, C))
+    return out
+
+
+@pytest.mark.parametrize("snap", snapshots(), ids=lambda s: s[0])
+@pytest.mark.parametrize("blocks", [1, 3, 8, 61, 256])
+def test_selection_bit_exact(S, snap, blocks):
+    import torch
+    name, f, a, y, C = snap
+    n = len(f)
+    rng = np.random.default_rng(blocks)
+    subsets = [np.arange(n), np.sort(rng.choice(n, size=n // 3, replace=False))]
+    for idx in subsets:
+        want = select_np(f, a, y, C, idx)
+        perm = rng.permutation(idx)            # the list order must not matter
+        t = lambda v, dt: torch.from_numpy(np.ascontiguousarray(v, dt)).cuda()
+        rc, got = S.svm_debug_select(t(perm, np.int32), t(f, np.float64), t(a, np.float64), t(y, np.int8), C,
+                                     num_blocks=blocks)
+        assert rc == 0
+        assert got[1] == want[1] and got[3] == want[3], (name, got, want)
+        assert np.float64(got[0]).tobytes() == np.float64(want[0]).tobytes()
+        assert np.float64(got[2]).tobytes() == np.float64(want[2]).tobytes()
+
+
+# ------------------------------------------------------------------ FP64 kernel values: trajectory parity
+
+def fp64_cases():
+    return [
+        ("cfg1_full_none", lambda: g.config1()),
+        ("cfg2_n3000_lazy_multi", lambda: sub(g.config2(), 3000)),
+        ("cfg2_n3000_earliest_single", lambda: sub(g.config2(heuristic=g.EARLIEST, mode=g.SHRINK_SINGLE), 3000)),
+        ("cfg2_n2500_random500_multi", lambda: sub(g.config2(heuristic=(g.KIND_FIXED, 500.0)), 2500)),
+        ("cfg4_n4000_lazy_multi", lambda: sub(g.config4(), 4000)),
+        ("cfg4_n3000_earliest_multi", lambda: sub(g.config4(heuristic=g.EARLIEST), 3000)),
+        ("cfg3_n1500_earliest_multi_slotmap", lambda: sub(g.config3(n=20_000), 1500)),
+    ]
+
+
+@pytest.mark.parametrize("case", fp64_cases(), ids=lambda c: c[0])
+def test_fp64_trajectory_and_contract(S, case):
+    name, make = case
+    cfg = make()
+    P("case", name, cfg.data.n, cfg.data.d, cfg.data.layout)
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP64, trace_cap=100_000)
+    assert out.rc == S.SVM_OK, S.strerror(out.rc)
+    ref = O.train_config(cfg, trace_cap=100_000)
+    assert out.result["iterations"] == ref.iterations
+    assert first_divergence(tr, ref.trace) == -1
+    assert out.result["n_recon"] == ref.n_recon
+    assert out.result["n_sv"] == ref.n_sv and out.result["n_bsv"] == ref.n_bsv
+    np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
+    np.testing.assert_allclose(out.f, ref.f, atol=1e-9)
+    rel, worst = check_contract(S, cfg, out, ref, S.SVM_KERNEL_FP64)
+    P("  iterations", ref.iterations, "dual rel %.2e decision %.2e" % (rel, worst))
+
+
+def test_feature_major_layout_is_identical(S):
+    import torch
+    cfg = g.config1(n=1500, d=9)
+    a = []
+    for lay in (S.SVM_DENSE_ROW_MAJOR, S.SVM_DENSE_FEATURE_MAJOR):
+        dp = S.to_device(cfg.data, layout=lay)
+        alpha = torch.zeros(cfg.data.n, dtype=torch.float64, device="cuda")
+        rc, res = S.svm_train(dp, S.params_for(cfg, kernel_precision=S.SVM_KERNEL_FP64), alpha)
+        assert rc == 0
+        a.append(alpha.cpu().numpy())
+    assert np.array_equal(a[0], a[1])
+
+
+# ------------------------------------------------------------------ FP32 kernel values
+
+def test_fp32_config1_full_contract(S):
+    cfg = g.config1()
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP32, trace_cap=10_000)
+    assert out.rc == S.SVM_OK
+    ref = O.train_config(cfg, trace_cap=10_000)
+    div = first_divergence(tr, ref.trace)
+    P("fp32 config1: iterations", out.result["iterations"], ref.iterations, "first divergence", div)
+    rel, worst = check_contract(S, cfg, out, ref, S.SVM_KERNEL_FP32)
+    P("  dual rel %.2e decision %.2e" % (rel, worst))
+
+
+def fresh_kkt(cfg, alpha, eps, slack=1e-6):
+    f = O.f_full(cfg.data, alpha, cfg.gamma)
+    y = cfg.data.y
+    bu, _, bl, _ = select_np(f, alpha, y, cfg.C)
+    assert np.all(alpha >= 0) and np.all(alpha <= cfg.C)
+    assert abs(np.dot(alpha, y)) <= 1e-9 * cfg.C * len(y)
+    assert bl - bu <= 2 * eps + slack, (bl - bu)
+    return f
+
+
+@pytest.mark.parametrize("case", [
+    ("cfg2_n3000_lazy_multi", lambda: sub(g.config2(), 3000)),
+    ("cfg4_n4000_lazy_multi", lambda: sub(g.config4(), 4000)),
+    ("cfg4_n3000_earliest_multi", lambda: sub(g.config4(heuristic=g.EARLIEST), 3000)),
+], ids=lambda c: c[0])
+def test_fp32_unique_quantities_and_validity(S, case):
+    name, make = case
+    cfg = make()
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP32, trace_cap=100_000)
+    assert out.rc == S.SVM_OK
+    ref = O.train_config(cfg, trace_cap=100_000)
+    D_gpu = O.dual(cfg.data, out.alpha, cfg.gamma)
+    D_ref = O.dual(cfg.data, ref.alpha, cfg.gamma)
+    rel = abs(D_gpu - D_ref) / abs(D_ref)
+    P(name, "first divergence", first_divergence(tr, ref.trace), "of", ref.iterations, "dual rel %.2e" % rel)
+    assert rel <= 1e-6
+    f = fresh_kkt(cfg, out.alpha, cfg.eps)
+    # the library's f and beta come from its closing recompute
+    assert np.abs(out.f - f).max() <= 1e-5
+    # decision kernel: GPU decision of the GPU model vs the oracle's decision of the same model
+    q = cfg.queries.subset(np.arange(1000))
+    dv = S.decision_data(cfg.data, out.alpha, out.result["beta"], cfg.gamma, q)
+    assert np.abs(dv - O.decision(cfg.data, out.alpha, out.result["beta"], cfg.gamma, q)).max() <= 1e-4
+
+
+@pytest.mark.parametrize("case", [
+    ("cfg2_n2000", lambda: sub(g.config2(), 2000)),
+    ("cfg4_n2500", lambda: sub(g.config4(), 2500)),
+], ids=lambda c: c[0])
+def test_fp32_tight_eps_matches_oracle_decisions(S, case):
+    """At a tight tolerance both runs sit at the unique optimum: decision values agree to 1e-4."""
+    name, make = case
+    cfg = make()
+    cfg.eps = 1e-5
+    out, _ = gpu_train(S, cfg, S.SVM_KERNEL_FP32)
+    ref = O.train_config(cfg)
+    assert out.rc == S.SVM_OK and ref.rc == 0
+    q = cfg.queries.subset(np.arange(1500))
+    dv = S.decision_data(cfg.data, out.alpha, out.result["beta"], cfg.gamma, q)
+    dref = O.decision(cfg.data, ref.alpha, ref.beta, cfg.gamma, q)
+    P(name, "tight-eps decision max abs %.2e" % np.abs(dv - dref).max())
+    assert np.abs(dv - dref).max() <= 1e-4
+
+
+# ------------------------------------------------------------------ decision kernel alone
+
+@pytest.mark.parametrize("layout", ["dense", "csr"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_decision_matches_oracle_for_any_alpha(S, layout, prec):
+    if layout == "dense":
+        cfg = g.config1(n=1700, d=33)
+    else:
+        cfg = sub(g.config2(), 1700)
+    rng = np.random.default_rng(11)
+    alpha = np.where(rng.random(cfg.data.n) < 0.4, rng.uniform(0, cfg.C, cfg.data.n), 0.0)
+    q = cfg.queries.subset(np.arange(777))
+    dv = S.decision_data(cfg.data, alpha, 0.0625, cfg.gamma, q, kernel_precision=prec)
+    dref = O.decision(cfg.data, alpha, 0.0625, cfg.gamma, q)
+    tol = 1e-4 if prec == 0 else 1e-11
+    assert np.abs(dv - dref).max() <= tol
+
+
+# ------------------------------------------------------------------ warm start: one step from a given state
+
+def test_one_step_from_oracle_state(S):
+    import torch
+    cfg = sub(g.config2(), 2000)
+    for k in (0, 3, 250):
+        st = O.train_config(cfg, max_iter=k)
+        nxt = O.train_config(cfg, max_iter=k + 1)
+        dp = S.to_device(cfg.data)
+        alpha = torch.from_numpy(st.alpha.copy()).cuda()
+        f = torch.from_numpy(st.f.copy()).cuda()
+        p = S.params_for(cfg, max_iter=1, kernel_precision=S.SVM_KERNEL_FP64,
+                         flags=S.SVM_FLAG_WARM_START | S.SVM_FLAG_NO_FINAL_RECOMPUTE)
+        p.shrink_mode = 0
+        rc, res = S.svm_train(dp, p, alpha, f)
+        assert rc == S.SVM_NOT_CONVERGED and res.iterations == 1
+        np.testing.assert_allclose(alpha.cpu().numpy(), nxt.alpha, atol=1e-13)
+        np.testing.assert_allclose(f.cpu().numpy(), nxt.f, atol=1e-12)
+
+
+# ------------------------------------------------------------------ error paths and caps
+
+def test_error_codes(S):
+    import torch
+    cfg = g.config1(n=300, d=4)
+    one = g.SvmData("one", 300, 4, "dense", np.ones(300, np.int8), x=cfg.data.x)
+    assert S.train_data(one, 1.0, 0.5).rc == S.SVM_EONECLASS
+    nanx = cfg.data.x.copy()
+    nanx[17, 2] = np.nan
+    assert S.train_data(g.SvmData("nan", 300, 4, "dense", cfg.data.y, x=nanx), 1.0, 0.5).rc == S.SVM_ENONFINITE
+    badlab = cfg.data.y.copy()
+    badlab[5] = 0
+    assert S.train_data(g.SvmData("lab", 300, 4, "dense", badlab, x=cfg.data.x), 1.0, 0.5).rc == S.SVM_EINVAL
+    c2 = sub(g.config2(), 500)
+    col = c2.data.col.copy()
+    r0, r1 = c2.data.row_ptr[3], c2.data.row_ptr[4]
+    col[r0:r1] = col[r0:r1][::-1]
+    bad = g.SvmData("unsorted", c2.data.n, c2.data.d, "csr", c2.data.y, row_ptr=c2.data.row_ptr, col=col,
+                    val=c2.data.val)
+    assert S.train_data(bad, 1.0, 0.01).rc == S.SVM_EINVAL
+    col2 = c2.data.col.copy()
+    col2[7] = 300
+    bad2 = g.SvmData("range", c2.data.n, c2.data.d, "csr", c2.data.y, row_ptr=c2.data.row_ptr, col=col2,
+                     val=c2.data.val)
+    assert S.train_data(bad2, 1.0, 0.01).rc == S.SVM_EINVAL
+    # workspace too small
+    dp = S.to_device(cfg.data)
+    p = S.params_for(cfg)
+    ws = torch.zeros(128, dtype=torch.uint8, device="cuda")
+    alpha = torch.zeros(300, dtype=torch.float64, device="cuda")
+    assert S.svm_train(dp, p, alpha, None, workspace=ws)[0] == S.SVM_EWORKSPACE
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_max_iter_cap_leaves_consistent_state(S, prec):
+    cfg = sub(g.config2(heuristic=g.EARLIEST), 2000)
+    out, _ = gpu_train(S, cfg, prec, max_iter=40)
+    assert out.rc == S.SVM_NOT_CONVERGED and out.result["iterations"] == 40
+    f = O.f_full(cfg.data, out.alpha, cfg.gamma)
+    assert np.abs(out.f - f).max() <= (1e-5 if prec == 0 else 1e-11)
+    if prec == 1:
+        ref = O.train_config(cfg, max_iter=40)
+        np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-12)
+
+
+def test_repeat_runs_are_bit_identical(S):
+    cfg = sub(g.config4(heuristic=g.EARLIEST), 3000)
+    a = gpu_train(S, cfg, S.SVM_KERNEL_FP32)[0]
+    b = gpu_train(S, cfg, S.SVM_KERNEL_FP32)[0]
+    assert np.array_equal(a.alpha, b.alpha) and np.array_equal(a.f, b.f)
