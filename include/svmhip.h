@@ -71,6 +71,8 @@ extern "C" {
 /* ---- flags */
 #define SVM_FLAG_WARM_START 1u         /* alpha and f are inputs: f must equal eq:fcache for alpha */
 #define SVM_FLAG_NO_FINAL_RECOMPUTE 2u /* skip the closing FP64-accumulated recompute of f and KKT re-check */
+#define SVM_FLAG_NO_LDS_PAYLOAD 4u     /* tuning/test: stream row payload from HBM even when it fits in LDS */
+#define SVM_FLAG_NO_LDS_STATE 8u       /* tuning/test: keep per-row state in HBM as well */
 
 /* A labelled (or, for queries, unlabelled) sample set.  All pointers are device pointers. */
 typedef struct {
@@ -184,6 +186,19 @@ int svm_debug_select(int32_t n_active, const int32_t* active, const double* f, c
  * up to `cap` records of (i_up, i_low) and (b_up, b_low) as selected before
  * each pair update (device arrays).  Pass cap = 0 to switch it off. */
 int svm_debug_set_trace(int64_t cap, int32_t* i_up, int32_t* i_low, double* b_up, double* b_low);
+
+/* Per-phase device timer of the SMO loop: when `slots` (device, 8 uint64) is
+ * non-NULL, workgroup 0 of every later svm_train on this host thread adds the
+ * wall-clock ticks (100 MHz) it spent in [0] pair staging and update, [1] the
+ * f-update / selection / shrink pass, [2] its block reduction, [3] the grid
+ * barrier wait, [4] the record merge, [5] the iteration count, [6] staging of
+ * the segment at launch, [7] the write-back at exit.  NULL switches it off. */
+int svm_debug_set_profile(uint64_t* slots);
+
+/* Residency mode (0 HBM, 1 per-row state in LDS, 2 state and rows in LDS),
+ * workgroups and CSR lanes per row chosen by the last svm_train on this host
+ * thread (host outputs, may be NULL). */
+int svm_debug_step_info(int32_t* mode, int32_t* grid_blocks, int32_t* lanes_per_row);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,238 @@
+// svm_device.h -- device helpers shared by the kernels of libsvmhip.so:
+// index-set tests on the status byte, the two-threshold reduction with its
+// lowest-index tie-break, the FP64 pair update, the grid barrier and the
+// dense distance of a row to the working pair.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "svm_internal.h"
+
+namespace svm {
+
+#define DEV __device__ __forceinline__
+
+constexpr double PAIR_TAU = 1e-12;    // floor for eta = K_uu + K_ll - 2 K_ul
+constexpr double PAIR_DELTA = 1e-12;  // alpha within DELTA*C of 0 or C is put on the bound
+constexpr int IDX_NONE = 0x7fffffff;  // empty side of a reduction
+
+// ------------------------------------------------------------------ small helpers
+
+DEV bool st_in_up(uint8_t s) {       // I0 u I1 u I2
+    return (s & ST_FREE) || ((s & ST_YPOS) ? !(s & ST_ATC) : (s & ST_ATC));
+}
+DEV bool st_in_low(uint8_t s) {      // I0 u I3 u I4
+    return (s & ST_FREE) || ((s & ST_YPOS) ? (s & ST_ATC) : !(s & ST_ATC));
+}
+DEV uint8_t st_make(bool ypos, double a, double C) {
+    uint8_t s = ypos ? ST_YPOS : 0;
+    if (a >= C) s |= ST_ATC;
+    else if (a > 0.0) s |= ST_FREE;
+    return s;
+}
+// eq:shrink: bound samples in I3 u I4 below b_up, or in I1 u I2 above b_low
+DEV bool shrink_rule(uint8_t s, double fi, double bu, double bl) {
+    if (s & ST_FREE) return false;
+    return (st_in_low(s) && fi < bu) || (st_in_up(s) && fi > bl);
+}
+
+DEV bool better_up(double v, int i, double bv, int bi) { return v < bv || (v == bv && i < bi); }
+DEV bool better_low(double v, int i, double bv, int bi) { return v > bv || (v == bv && i < bi); }
+
+// DPP lane moves (gfx9 encodings): xor 1 and 2 inside a quad, rotate by 4 and 8 inside a
+// 16-lane row, then lane 15 -> next row and lane 31 -> rows 2-3.  Lanes a move does not
+// write keep `old`, which is always the reduction's identity here.
+constexpr int DPP_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_ROR4 = 0x124;     // row_ror:4
+constexpr int DPP_ROR8 = 0x128;     // row_ror:8
+constexpr int DPP_BCAST15 = 0x142;  // row_bcast:15
+constexpr int DPP_BCAST31 = 0x143;  // row_bcast:31
+
+template <int CTRL, int ROWS>
+DEV int dpp_i(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+DEV double dpp_d(double old, double v) {
+    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL, ROWS>((int)(unsigned)(o & 0xffffffffll), (int)(unsigned)(x & 0xffffffffll));
+    const int hi = dpp_i<CTRL, ROWS>((int)(o >> 32), (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL, int ROWS>
+DEV void sel_step(double& bu, int& iu, double& bl, int& il) {
+    const double ou = dpp_d<CTRL, ROWS>(INFINITY, bu);
+    const int oiu = dpp_i<CTRL, ROWS>(IDX_NONE, iu);
+    const double ol = dpp_d<CTRL, ROWS>(-INFINITY, bl);
+    const int oil = dpp_i<CTRL, ROWS>(IDX_NONE, il);
+    if (better_up(ou, oiu, bu, iu)) { bu = ou; iu = oiu; }
+    if (better_low(ol, oil, bl, il)) { bl = ol; il = oil; }
+}
+
+// Wave-wide two-threshold reduction; the result is valid in lane 63 (and returned in every lane
+// by wave_reduce_sel).  Only DPP moves: no LDS traffic.
+DEV void wave_reduce_sel_to63(double& bu, int& iu, double& bl, int& il) {
+    sel_step<DPP_XOR1, 0xF>(bu, iu, bl, il);
+    sel_step<DPP_XOR2, 0xF>(bu, iu, bl, il);
+    sel_step<DPP_ROR4, 0xF>(bu, iu, bl, il);
+    sel_step<DPP_ROR8, 0xF>(bu, iu, bl, il);
+    sel_step<DPP_BCAST15, 0xA>(bu, iu, bl, il);
+    sel_step<DPP_BCAST31, 0xC>(bu, iu, bl, il);
+}
+
+DEV double readlane_d(double v, int lane) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)(x & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+DEV void wave_reduce_sel(double& bu, int& iu, double& bl, int& il) {
+    wave_reduce_sel_to63(bu, iu, bl, il);
+    bu = readlane_d(bu, 63);
+    iu = __builtin_amdgcn_readlane(iu, 63);
+    bl = readlane_d(bl, 63);
+    il = __builtin_amdgcn_readlane(il, 63);
+}
+
+template <typename T>
+DEV T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+DEV float kexp(float v) { return expf(v); }
+DEV double kexp(double v) { return exp(v); }
+
+DEV double ld_agent(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+DEV void st_agent(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+DEV unsigned long long ld_agent(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void st_agent(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int BLOCK>
+DEV void block_reduce_sel_all(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i);
+
+// Block-wide reduction of the selection candidates; result valid in every thread.
+template <int BLOCK>
+DEV void block_reduce_sel(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i) {
+    constexpr int NW = BLOCK / 64;
+    block_reduce_sel_all<BLOCK>(bu, iu, bl, il, s_v, s_i);
+    __syncthreads();
+}
+
+// Block-wide reduction whose result every thread holds on return; one barrier.  The
+// caller must not overwrite s_v / s_i before the next barrier.
+template <int BLOCK>
+DEV void block_reduce_sel_all(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i) {
+    constexpr int NW = BLOCK / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    wave_reduce_sel_to63(bu, iu, bl, il);
+    if (lane == 63) {
+        s_v[wid] = bu; s_i[wid] = iu;
+        s_v[NW + wid] = bl; s_i[NW + wid] = il;
+    }
+    __syncthreads();
+    bu = s_v[0]; iu = s_i[0]; bl = s_v[NW]; il = s_i[NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        const double vu = s_v[w], vl = s_v[NW + w];
+        const int ju = s_i[w], jl = s_i[NW + w];
+        if (better_up(vu, ju, bu, iu)) { bu = vu; iu = ju; }
+        if (better_low(vl, jl, bl, il)) { bl = vl; il = jl; }
+    }
+}
+
+// ------------------------------------------------------------------ pair update (eq:alphaup, eq:rho)
+
+struct PairNew {
+    double au, al;            // new alpha of the pair
+    double cu, cl;            // y_up * d_alpha_up, y_low * d_alpha_low
+};
+
+DEV double snap_bound(double a, double C) {
+    if (a < PAIR_DELTA * C) return 0.0;
+    if (a > C - PAIR_DELTA * C) return C;
+    return a;
+}
+
+// K(up,up) = K(low,low) = 1 for the Gaussian kernel, so eta = 2 - 2 K_ul (= -rho).
+DEV PairNew pair_update(double au, double al, int yu, int yl, double bu, double bl, double Kul, double C) {
+    double eta = 2.0 - 2.0 * Kul;
+    if (eta < PAIR_TAU) eta = PAIR_TAU;
+    const double s = (double)(yu * yl);
+    double L, H;
+    if (yu != yl) {
+        L = fmax(0.0, al - au);
+        H = fmin(C, C + al - au);
+    } else {
+        L = fmax(0.0, al + au - C);
+        H = fmin(C, al + au);
+    }
+    double nl = al + (double)yl * (bu - bl) / eta;
+    nl = fmin(fmax(nl, L), H);
+    double nu = au + s * (al - nl);
+    PairNew p;
+    p.al = snap_bound(nl, C);
+    p.au = snap_bound(nu, C);
+    p.cu = (double)yu * (p.au - au);
+    p.cl = (double)yl * (p.al - al);
+    return p;
+}
+
+// ------------------------------------------------------------------ kernel rows of the pair
+
+// Dense: squared distances of row xr to the pair (u, l) held in LDS as float2,
+// by direct difference in the order k = 0..dpad-1 (padding contributes 0).
+template <typename KT>
+DEV void dense_dist(const float* __restrict__ xr, const float2* __restrict__ pair, int dpad, KT& su, KT& sl) {
+    const float4* x4 = reinterpret_cast<const float4*>(xr);
+    const float4* p4 = reinterpret_cast<const float4*>(pair);
+    if constexpr (std::is_same<KT, double>::value) {
+#pragma clang fp contract(off)
+        double a = 0.0, b = 0.0;
+        for (int k4 = 0; k4 < dpad / 4; ++k4) {
+            float4 v = x4[k4];
+            float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];   // (u0 l0 u1 l1) (u2 l2 u3 l3)
+            double t;
+            t = (double)v.x - (double)q0.x; a = a + t * t;
+            t = (double)v.x - (double)q0.y; b = b + t * t;
+            t = (double)v.y - (double)q0.z; a = a + t * t;
+            t = (double)v.y - (double)q0.w; b = b + t * t;
+            t = (double)v.z - (double)q1.x; a = a + t * t;
+            t = (double)v.z - (double)q1.y; b = b + t * t;
+            t = (double)v.w - (double)q1.z; a = a + t * t;
+            t = (double)v.w - (double)q1.w; b = b + t * t;
+        }
+        su = a; sl = b;
+    } else {
+        float a = 0.f, b = 0.f;
+        for (int k4 = 0; k4 < dpad / 4; ++k4) {
+            float4 v = x4[k4];
+            float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
+            float t;
+            t = v.x - q0.x; a = fmaf(t, t, a);
+            t = v.x - q0.y; b = fmaf(t, t, b);
+            t = v.y - q0.z; a = fmaf(t, t, a);
+            t = v.y - q0.w; b = fmaf(t, t, b);
+            t = v.z - q1.x; a = fmaf(t, t, a);
+            t = v.z - q1.y; b = fmaf(t, t, b);
+            t = v.w - q1.z; a = fmaf(t, t, a);
+            t = v.w - q1.w; b = fmaf(t, t, b);
+        }
+        su = a; sl = b;
+    }
+}
+
+
+}  // namespace svm

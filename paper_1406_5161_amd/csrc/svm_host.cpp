@@ -41,6 +41,14 @@ TraceCfg& trace_cfg() {
     static thread_local TraceCfg t;
     return t;
 }
+int* last_step_info() {
+    static thread_local int v[3] = {0, 0, 0};
+    return v;
+}
+unsigned long long*& prof_cfg() {
+    static thread_local unsigned long long* p = nullptr;
+    return p;
+}
 
 constexpr int NSPLIT_MAX = 16;
 constexpr size_t ALIGN = 256;
@@ -71,7 +79,7 @@ Plan make_plan(const svm_problem_t* p) {
     q.act = take(sizeof(int32_t) * n);
     q.seg = take(sizeof(int32_t) * (MAX_GRID + 1));
     q.cnt = take(sizeof(int32_t) * MAX_GRID);
-    q.rec = take(sizeof(Rec) * 2 * MAX_GRID);
+    q.rec = take(sizeof(Rec) * 3 * MAX_GRID);   // [0, 2G): tagged step records; [2G, 3G): selection
     q.listw = take(sizeof(int32_t) * n);
     q.listz = take(sizeof(int32_t) * n);
     q.coef = take(sizeof(double) * n);
@@ -155,6 +163,9 @@ struct Solver {
     double ms_step = 0, ms_recon = 0;
     int n_launch = 0;
     unsigned long long* work = nullptr;
+    StepLds plan_lds{};
+    int nseg_max = 0;
+    long long nnz_seg_max = 0;
     unsigned long long rows_streamed = 0, nnz_streamed = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     ~Solver() {
@@ -176,7 +187,7 @@ struct Solver {
     }
 
     int select_all() {
-        HIP_TRY(launch_select(G, seg, cnt, act, f, alpha, p->y, q->C, rec, ctl, s));
+        HIP_TRY(launch_select(G, seg, cnt, act, f, alpha, p->y, q->C, rec + 2 * MAX_GRID, ctl, s));
         return read_ctl();
     }
 
@@ -265,9 +276,15 @@ struct Solver {
         a.trace_cap = t.cap; a.tr_iu = t.iu; a.tr_il = t.il; a.tr_bu = t.bu; a.tr_bl = t.bl;
         a.spin_limit = 500ull * 1000 * 1000;   // 5 s of the 100 MHz wall clock per barrier wait
         a.work = work;
+        a.mode = plan_lds.mode;
+        a.nseg_max = nseg_max;
+        a.nnz_seg_max = (int32_t)nnz_seg_max;
+        a.lds_meta_off = (int32_t)plan_lds.meta_off;
+        a.lds_pay_off = (int32_t)plan_lds.pay_off;
+        a.prof = prof_cfg();
         HIP_TRY(hipMemsetAsync(bar, 0, sizeof(unsigned long long), s));
         HIP_TRY(hipEventRecord(ev0, s));
-        HIP_TRY(launch_step(a, G, lpr, q->kernel_precision, s));
+        HIP_TRY(launch_step(a, G, lpr, q->kernel_precision, plan_lds.total, s));
         HIP_TRY(hipEventRecord(ev1, s));
         int rc = read_ctl();
         if (rc) return rc;
@@ -286,12 +303,6 @@ int64_t heuristic_h(const svm_params_t* q, int n) {
     double h = q->shrink_kind == SVM_KIND_FIXED ? q->shrink_param : std::ceil(q->shrink_param * (double)n);
     if (h < 1) h = 1;
     return (int64_t)h;
-}
-
-int choose_lpr(const svm_problem_t* p, const svm_params_t* q) {
-    if (p->layout != SVM_CSR) return 1;
-    if (q->lanes_per_row) return q->lanes_per_row;
-    return -1;  // filled once nnz is known
 }
 
 int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, double* f_out, svm_result_t* out,
@@ -322,6 +333,8 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
     S.sumblk = S.at<double>(S.plan.sumblk);
     S.out6 = S.at<double>(S.plan.out6);
     S.work = S.at<unsigned long long>(S.plan.work);
+    // records carry iteration tags: clear them so no stale tag of an earlier solve can match
+    HIP_TRY(hipMemsetAsync(S.rec, 0, sizeof(Rec) * 2 * MAX_GRID, s));
     HIP_TRY(hipEventCreate(&S.ev0));
     HIP_TRY(hipEventCreate(&S.ev1));
 
@@ -348,13 +361,7 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
         S.pattern_only = notpat == 0;
         S.lay = p->d <= TABLE_MAX_D ? LAY_CSR_TABLE : LAY_CSR_SLOT;
         if (S.lay == LAY_CSR_SLOT && S.max_row_nnz > SLOT_MAX_NNZ) return SVM_EUNSUPPORTED;
-        S.lpr = choose_lpr(p, q);
-        if (S.lpr < 0) {
-            double avg = (double)nnz / (double)p->n;
-            int l = 1;
-            while (l < 32 && 4 * l * 2 <= avg) l *= 2;
-            S.lpr = l;
-        }
+        S.lpr = q->lanes_per_row ? q->lanes_per_row : 1;   // refined with the LDS plan below
         S.xin = nullptr;
     } else {
         S.lay = LAY_DENSE;
@@ -365,15 +372,60 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
         S.xin = xp;
     }
 
-    // ---- grid size: co-resident workgroups (cooperative launch), about 1024 rows each
-    const size_t lds = step_lds_bytes(S.lay, S.d, S.dpad, S.max_row_nnz);
-    if (lds > 160 * 1024) return SVM_EUNSUPPORTED;
-    int maxG = std::min(MAX_GRID, step_max_blocks(S.lay, S.lpr, q->kernel_precision, lds));
-    if (maxG < 1) return SVM_EUNSUPPORTED;
-    int G = q->grid_blocks ? q->grid_blocks : std::max(1, (p->n + 1023) / 1024);
-    G = std::min(G, maxG);
+    // ---- grid size and residency: co-resident workgroups (cooperative launch), each owning a
+    // segment of about `rows_target` samples, kept in LDS when it fits
+    std::vector<int32_t> hrp;
+    if (p->layout == SVM_CSR) {
+        hrp.resize((size_t)p->n + 1);
+        HIP_TRY(hipMemcpyAsync(hrp.data(), p->row_ptr, sizeof(int32_t) * hrp.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    const int max_mode = (q->flags & SVM_FLAG_NO_LDS_STATE) ? STEP_GLOBAL
+                       : (q->flags & SVM_FLAG_NO_LDS_PAYLOAD) ? STEP_LDS_STATE : STEP_LDS_ALL;
+    // Shape rules from per-phase timings of the loop on gfx950: one workgroup (no exchange at
+    // all) up to 4096 samples; beyond that about 800 samples per workgroup, at most 192
+    // workgroups (every workgroup reads every record, so the exchange grows with G^2).
+    const int cus = std::max(1, device_cu_count());
+    int G = q->grid_blocks;
+    if (!G) G = p->n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 192), (p->n + 400) / 800));
     G = std::min(G, p->n);
+    const double avg_nnz = p->layout == SVM_CSR ? (double)hrp[p->n] / (double)p->n : 0.0;
+    StepLds plan{};
+    for (int tries = 0;; ++tries) {
+        const int nseg_max = (p->n + G - 1) / G;
+        long long nnz_seg_max = 0;
+        if (!hrp.empty())
+            for (int b = 0; b < G; ++b) {
+                const int s0 = (int)(((long long)p->n * b) / G), s1 = (int)(((long long)p->n * (b + 1)) / G);
+                nnz_seg_max = std::max<long long>(nnz_seg_max, hrp[s1] - hrp[s0]);
+            }
+        plan = plan_step_lds(S.lay, S.d, S.dpad, S.max_row_nnz, nseg_max, nnz_seg_max, S.pattern_only, max_mode);
+        if (plan.total > STEP_LDS_BUDGET) return SVM_EUNSUPPORTED;
+        if (p->layout == SVM_CSR && !q->lanes_per_row) {
+            // rows in LDS: few lanes per row (short LDS chains, no cross-lane reduction);
+            // rows from HBM: enough lanes for coalesced row reads
+            int l = 1;
+            if (plan.mode == STEP_LDS_ALL) l = avg_nnz < 48 ? 2 : 4;
+            else while (l < 32 && 16.0 * l <= avg_nnz) l *= 2;
+            S.lpr = l;
+        }
+        const int maxG = std::min(MAX_GRID, step_max_blocks(S.lay, S.lpr, q->kernel_precision, plan.mode, plan.total));
+        if (maxG < 1) return SVM_EUNSUPPORTED;
+        if (G <= maxG || tries > 4) { G = std::min(G, maxG); break; }
+        G = maxG;
+    }
     S.G = G;
+    S.plan_lds = plan;
+    last_step_info()[0] = plan.mode;
+    last_step_info()[1] = G;
+    last_step_info()[2] = S.lpr;
+    S.nseg_max = (p->n + G - 1) / G;
+    S.nnz_seg_max = 0;
+    if (!hrp.empty())
+        for (int b = 0; b < G; ++b) {
+            const int s0 = (int)(((long long)p->n * b) / G), s1 = (int)(((long long)p->n * (b + 1)) / G);
+            S.nnz_seg_max = std::max<long long>(S.nnz_seg_max, hrp[s1] - hrp[s0]);
+        }
 
     // ---- initial state: alpha = 0, f = -y (or the caller's warm start), everything active
     const bool warm = (q->flags & SVM_FLAG_WARM_START) != 0;
@@ -619,6 +671,18 @@ int svm_debug_set_trace(int64_t cap, int32_t* i_up, int32_t* i_low, double* b_up
     if (cap < 0 || (cap > 0 && (!i_up || !i_low || !b_up || !b_low))) return SVM_EINVAL;
     TraceCfg& t = trace_cfg();
     t.cap = cap; t.iu = i_up; t.il = i_low; t.bu = b_up; t.bl = b_low;
+    return SVM_OK;
+}
+
+int svm_debug_set_profile(uint64_t* slots) {
+    prof_cfg() = reinterpret_cast<unsigned long long*>(slots);
+    return SVM_OK;
+}
+
+int svm_debug_step_info(int32_t* mode, int32_t* grid_blocks, int32_t* lanes_per_row) {
+    if (mode) *mode = last_step_info()[0];
+    if (grid_blocks) *grid_blocks = last_step_info()[1];
+    if (lanes_per_row) *lanes_per_row = last_step_info()[2];
     return SVM_OK;
 }
 

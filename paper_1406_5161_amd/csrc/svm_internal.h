@@ -31,6 +31,7 @@ enum : uint8_t { ST_YPOS = 1, ST_FREE = 2, ST_ATC = 4 };
 // launches of the persistent loop.
 struct Ctl {
     double b_up, b_low;
+    double a_up, a_low;       // alpha of the selected pair (carried, never re-read inside a launch)
     int32_t i_up, i_low;
     int64_t iter;
     int64_t counter;          // iterations left until the next shrink pass
@@ -46,9 +47,14 @@ struct Ctl {
 };
 static_assert(sizeof(Ctl) <= 256, "Ctl must fit in its slot");
 
-// One workgroup's partial selection: (b_up bits, b_low bits, i_up | i_low << 32, active count).
+// One workgroup's partial selection for one iteration, in its own 128-byte line.  Every
+// 64-bit word is self-validating: the high half is the iteration tag, the low half a
+// 32-bit fragment of (b_up, b_low, i_up, i_low, active count, alpha_up, alpha_low and
+// the CSR extents of the two candidates), so readers need no fence or barrier: a
+// record is complete when all its words carry the current tag.
+constexpr int REC_WORDS = 15;
 struct Rec {
-    unsigned long long w[4];
+    unsigned long long w[16];
 };
 
 struct StepArgs {
@@ -79,7 +85,31 @@ struct StepArgs {
     double* tr_bl;
     unsigned long long spin_limit;  // watchdog for one barrier wait (wall-clock ticks)
     unsigned long long* work;       // [G][2]: rows and nonzeros streamed by each workgroup in this launch
+    // where each workgroup keeps its segment during a launch
+    int32_t mode;             // STEP_GLOBAL, STEP_LDS_STATE or STEP_LDS_ALL
+    int32_t nseg_max;         // rows of the largest segment
+    int32_t lds_meta_off;     // byte offset of the per-row state in dynamic LDS
+    int32_t lds_pay_off;      // byte offset of the resident row payload
+    int32_t nnz_seg_max;      // CSR: nonzeros of the largest segment
+    int32_t pad2;
+    unsigned long long* prof; // [PROF_SLOTS] phase times of workgroup 0 (wall-clock ticks), or NULL
 };
+
+// Residency of a workgroup's segment during one launch of the SMO loop:
+// STEP_GLOBAL    per-row state (f, status, active list) and row payload in HBM;
+// STEP_LDS_STATE per-row state in LDS, row payload streamed from HBM;
+// STEP_LDS_ALL   per-row state and row payload (dense rows or CSR column ids
+//                as u16, plus values unless all are 1.0) in LDS.
+enum : int { STEP_GLOBAL = 0, STEP_LDS_STATE = 1, STEP_LDS_ALL = 2 };
+constexpr int PROF_SLOTS = 8;
+constexpr size_t STEP_LDS_BUDGET = 156 * 1024;
+
+struct StepLds {
+    size_t pair_bytes, meta_off, pay_off, total;
+    int mode;
+};
+StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, long long nnz_seg_max,
+                      bool pattern_only, int max_mode);
 
 // Kernel sums: out[a] = sum_b coef[b] * K(A_a, B_b) + bias_a, bias_a = -y_a or -beta.
 struct SumArgs {
@@ -117,9 +147,8 @@ hipError_t launch_init_state(int n, const int8_t* y, double C, int warm, double*
 hipError_t launch_reset_active(int n, int G, int32_t* seg_start, int32_t* cnt, int32_t* act, hipStream_t s);
 hipError_t launch_select(int G, const int32_t* seg_start, const int32_t* cnt, const int32_t* act, const double* f,
                          const double* alpha, const int8_t* y, double C, Rec* rec, Ctl* ctl, hipStream_t s);
-hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, hipStream_t s);
-size_t step_lds_bytes(int lay, int d, int dpad, int max_row_nnz);
-int step_max_blocks(int lay, int lpr, int kprec, size_t lds);
+hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, size_t lds, hipStream_t s);
+int step_max_blocks(int lay, int lpr, int kprec, int mode, size_t lds);
 hipError_t launch_mark_active(int n, int G, const int32_t* seg_start, const int32_t* cnt, const int32_t* act,
                               uint8_t* mask, hipStream_t s);
 // stable compaction: list = ascending ids i with pred(i); pred: 0 = mask[i]==0, 1 = alpha[i] > 0, 2 = all
@@ -134,7 +163,6 @@ hipError_t launch_refresh_status(int n, const double* alpha, const int8_t* y, do
 // final scalars: [0] sum f over I0, [1] |I0|, [2] sum alpha, [3] sum alpha y (f + y), [4] n_sv, [5] n_bsv
 hipError_t launch_summary(int n, const double* alpha, const double* f, const int8_t* y, double C, double* blk,
                           double* out6, hipStream_t s);
-hipError_t launch_csr_row_norm_max(int n, const int32_t* rp, Ctl* ctl, hipStream_t s);
 hipError_t launch_check_pattern(int nnz, const float* val, int32_t* flag, hipStream_t s);
 
 int device_cu_count();

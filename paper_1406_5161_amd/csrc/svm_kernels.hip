@@ -1,13 +1,9 @@
-// svm_kernels.hip -- device code of libsvmhip.so for gfx950 (CDNA4, wave64).
-//
-// The SMO step of the paper (Alg. 2 / Alg. 4: pair update, f update of eq:fup
-// over the active set, two-threshold selection of eq:bminmax, shrink rule of
-// eq:shrink) runs as ONE persistent cooperative launch per driver phase:
-// every workgroup owns a fixed slice of the samples, keeps its active list
-// compacted in place, and the workgroups meet once per iteration at a grid
-// barrier to merge their (b_up, i_up, b_low, i_low) records.  Everything the
-// paper does with MPI_Bcast / MPI_Allreduce / GA get-put becomes LDS staging
-// of the working pair, wave64 shuffle reductions and one barrier.
+// svm_kernels.hip -- set-up and support kernels of libsvmhip.so for gfx950:
+// input validation, dense packing, state initialisation, the initial and
+// post-reconstruction selection, stable compaction of id lists, the kernel
+// sums behind gradient reconstruction (Alg. 6) and the classifier
+// (eq:classi), and the closing reductions (threshold, dual objective).
+// The persistent SMO loop itself is in svm_step.hip.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -15,620 +11,10 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "svm_device.h"
 #include "svm_internal.h"
 
 namespace svm {
-
-#define DEV __device__ __forceinline__
-
-constexpr double PAIR_TAU = 1e-12;    // floor for eta = K_uu + K_ll - 2 K_ul
-constexpr double PAIR_DELTA = 1e-12;  // alpha within DELTA*C of 0 or C is put on the bound
-constexpr int IDX_NONE = 0x7fffffff;  // empty side of a reduction
-
-// ------------------------------------------------------------------ small helpers
-
-DEV bool st_in_up(uint8_t s) {       // I0 u I1 u I2
-    return (s & ST_FREE) || ((s & ST_YPOS) ? !(s & ST_ATC) : (s & ST_ATC));
-}
-DEV bool st_in_low(uint8_t s) {      // I0 u I3 u I4
-    return (s & ST_FREE) || ((s & ST_YPOS) ? (s & ST_ATC) : !(s & ST_ATC));
-}
-DEV uint8_t st_make(bool ypos, double a, double C) {
-    uint8_t s = ypos ? ST_YPOS : 0;
-    if (a >= C) s |= ST_ATC;
-    else if (a > 0.0) s |= ST_FREE;
-    return s;
-}
-// eq:shrink: bound samples in I3 u I4 below b_up, or in I1 u I2 above b_low
-DEV bool shrink_rule(uint8_t s, double fi, double bu, double bl) {
-    if (s & ST_FREE) return false;
-    return (st_in_low(s) && fi < bu) || (st_in_up(s) && fi > bl);
-}
-
-DEV bool better_up(double v, int i, double bv, int bi) { return v < bv || (v == bv && i < bi); }
-DEV bool better_low(double v, int i, double bv, int bi) { return v > bv || (v == bv && i < bi); }
-
-DEV void wave_reduce_sel(double& bu, int& iu, double& bl, int& il) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double ou = __shfl_xor(bu, off);
-        int oiu = __shfl_xor(iu, off);
-        double ol = __shfl_xor(bl, off);
-        int oil = __shfl_xor(il, off);
-        if (better_up(ou, oiu, bu, iu)) { bu = ou; iu = oiu; }
-        if (better_low(ol, oil, bl, il)) { bl = ol; il = oil; }
-    }
-}
-
-template <typename T>
-DEV T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-DEV float kexp(float v) { return expf(v); }
-DEV double kexp(double v) { return exp(v); }
-
-DEV double ld_agent(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-DEV void st_agent(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-DEV unsigned long long ld_agent(const unsigned long long* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-DEV void st_agent(unsigned long long* p, unsigned long long v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Block-wide reduction of the selection candidates; result valid in thread 0.
-template <int BLOCK>
-DEV void block_reduce_sel(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i) {
-    constexpr int NW = BLOCK / 64;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    wave_reduce_sel(bu, iu, bl, il);
-    if (lane == 0) {
-        s_v[wid] = bu; s_i[wid] = iu;
-        s_v[NW + wid] = bl; s_i[NW + wid] = il;
-    }
-    __syncthreads();
-    if (wid == 0) {
-        bu = lane < NW ? s_v[lane] : INFINITY;
-        iu = lane < NW ? s_i[lane] : IDX_NONE;
-        bl = lane < NW ? s_v[NW + lane] : -INFINITY;
-        il = lane < NW ? s_i[NW + lane] : IDX_NONE;
-        wave_reduce_sel(bu, iu, bl, il);
-    }
-    __syncthreads();
-}
-
-// ------------------------------------------------------------------ pair update (eq:alphaup, eq:rho)
-
-struct PairNew {
-    double au, al;            // new alpha of the pair
-    double cu, cl;            // y_up * d_alpha_up, y_low * d_alpha_low
-};
-
-DEV double snap_bound(double a, double C) {
-    if (a < PAIR_DELTA * C) return 0.0;
-    if (a > C - PAIR_DELTA * C) return C;
-    return a;
-}
-
-// K(up,up) = K(low,low) = 1 for the Gaussian kernel, so eta = 2 - 2 K_ul (= -rho).
-DEV PairNew pair_update(double au, double al, int yu, int yl, double bu, double bl, double Kul, double C) {
-    double eta = 2.0 - 2.0 * Kul;
-    if (eta < PAIR_TAU) eta = PAIR_TAU;
-    const double s = (double)(yu * yl);
-    double L, H;
-    if (yu != yl) {
-        L = fmax(0.0, al - au);
-        H = fmin(C, C + al - au);
-    } else {
-        L = fmax(0.0, al + au - C);
-        H = fmin(C, al + au);
-    }
-    double nl = al + (double)yl * (bu - bl) / eta;
-    nl = fmin(fmax(nl, L), H);
-    double nu = au + s * (al - nl);
-    PairNew p;
-    p.al = snap_bound(nl, C);
-    p.au = snap_bound(nu, C);
-    p.cu = (double)yu * (p.au - au);
-    p.cl = (double)yl * (p.al - al);
-    return p;
-}
-
-// ------------------------------------------------------------------ grid barrier
-
-// Monotone counter barrier across the co-resident workgroups of a cooperative
-// launch.  Release/acquire at agent scope publish the records and alpha writes.
-DEV bool grid_barrier(unsigned long long* bar, unsigned long long target, int* abort_flag,
-                      unsigned long long spin_limit, int* s_flag) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long t0 = wall_clock64();
-        int ab = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
-            if (wall_clock64() - t0 > spin_limit) {
-                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ab = 1;
-                break;
-            }
-        }
-        *s_flag = ab;
-    }
-    __syncthreads();
-    return *s_flag == 0;
-}
-
-// ------------------------------------------------------------------ kernel rows of the pair
-
-// Dense: squared distances of row xr to the pair (u, l) held in LDS as float2,
-// by direct difference in the order k = 0..dpad-1 (padding contributes 0).
-template <typename KT>
-DEV void dense_dist(const float* __restrict__ xr, const float2* __restrict__ pair, int dpad, KT& su, KT& sl) {
-    const float4* x4 = reinterpret_cast<const float4*>(xr);
-    const float4* p4 = reinterpret_cast<const float4*>(pair);
-    if constexpr (std::is_same<KT, double>::value) {
-#pragma clang fp contract(off)
-        double a = 0.0, b = 0.0;
-        for (int k4 = 0; k4 < dpad / 4; ++k4) {
-            float4 v = x4[k4];
-            float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];   // (u0 l0 u1 l1) (u2 l2 u3 l3)
-            double t;
-            t = (double)v.x - (double)q0.x; a = a + t * t;
-            t = (double)v.x - (double)q0.y; b = b + t * t;
-            t = (double)v.y - (double)q0.z; a = a + t * t;
-            t = (double)v.y - (double)q0.w; b = b + t * t;
-            t = (double)v.z - (double)q1.x; a = a + t * t;
-            t = (double)v.z - (double)q1.y; b = b + t * t;
-            t = (double)v.w - (double)q1.z; a = a + t * t;
-            t = (double)v.w - (double)q1.w; b = b + t * t;
-        }
-        su = a; sl = b;
-    } else {
-        float a = 0.f, b = 0.f;
-        for (int k4 = 0; k4 < dpad / 4; ++k4) {
-            float4 v = x4[k4];
-            float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
-            float t;
-            t = v.x - q0.x; a = fmaf(t, t, a);
-            t = v.x - q0.y; b = fmaf(t, t, b);
-            t = v.y - q0.z; a = fmaf(t, t, a);
-            t = v.y - q0.w; b = fmaf(t, t, b);
-            t = v.z - q1.x; a = fmaf(t, t, a);
-            t = v.z - q1.y; b = fmaf(t, t, b);
-            t = v.w - q1.z; a = fmaf(t, t, a);
-            t = v.w - q1.w; b = fmaf(t, t, b);
-        }
-        su = a; sl = b;
-    }
-}
-
-// ------------------------------------------------------------------ the persistent SMO loop
-
-template <int LAY, typename KT, int LPR>
-__global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
-    constexpr int BLOCK = STEP_BLOCK;
-    constexpr int NW = BLOCK / 64;
-    constexpr int NG = BLOCK / LPR;
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double s_v[2 * NW];
-    __shared__ int s_i[2 * NW];
-    __shared__ int s_wc[NW];
-    __shared__ int s_flag;
-    __shared__ double s_pair[4];     // K_ul, |u|^2, |l|^2
-    __shared__ double s_sel[2];
-    __shared__ int s_seli[3];
-    __shared__ int s_prev_n;
-
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int g = tid / LPR, gl = tid % LPR;
-    const int blk = blockIdx.x, G = gridDim.x;
-    const double C = A.C;
-
-    // LDS carve-up: pair staging area, then the previous pair's columns (CSR)
-    float2* pairv = reinterpret_cast<float2*>(smem);
-    uint16_t* slot = nullptr;
-    int* prev_cols = nullptr;
-    if (LAY == LAY_DENSE) {
-        // pairv[dpad]
-    } else if (LAY == LAY_CSR_TABLE) {
-        prev_cols = reinterpret_cast<int*>(smem + sizeof(float2) * (size_t)A.d);
-        for (int k = tid; k < A.d; k += BLOCK) pairv[k] = make_float2(0.f, 0.f);
-    } else {
-        // vals[1 + 2*maxnnz] float2, slot[d] u16, prev_cols[2*maxnnz]
-        const int nv = 1 + 2 * A.max_row_nnz;
-        slot = reinterpret_cast<uint16_t*>(smem + sizeof(float2) * (size_t)nv);
-        prev_cols = reinterpret_cast<int*>(smem + sizeof(float2) * (size_t)nv + ((sizeof(uint16_t) * (size_t)A.d + 15) & ~(size_t)15));
-        for (int k = tid; k < A.d; k += BLOCK) slot[k] = 0;
-        if (tid == 0) pairv[0] = make_float2(0.f, 0.f);
-    }
-    if (tid == 0) s_prev_n = 0;
-
-    // solver state (identical in every workgroup)
-    Ctl* ctl = A.ctl;
-    double bu = ctl->b_up, bl = ctl->b_low;
-    int iu = ctl->i_up, il = ctl->i_low;
-    long long iter = ctl->iter, counter = ctl->counter, n_act_total = ctl->n_active;
-    long long passes = ctl->shrink_passes, shrunk = ctl->shrunk_total;
-    const int seg0 = A.seg_start[blk];
-    int nrows = A.cnt[blk];
-    int32_t* lst = A.act + seg0;
-    int exit_reason = EXIT_NONE;
-    unsigned long long bar_target = 0;
-    unsigned long long work_rows = 0, work_nnz = 0;
-    __syncthreads();
-
-    for (;;) {
-        if (!(bl - bu > A.thr)) { exit_reason = EXIT_CONVERGED; break; }
-        if (iter >= A.max_iter) { exit_reason = EXIT_MAXITER; break; }
-        if (blk == 0 && tid == 0 && iter < A.trace_cap) {
-            A.tr_iu[iter] = iu; A.tr_il[iter] = il; A.tr_bu[iter] = bu; A.tr_bl[iter] = bl;
-        }
-        // ---- the working pair: alpha, labels, rows into LDS (the paper's broadcast of x_up, x_low)
-        const double au = ld_agent(A.alpha + iu);
-        const double al = ld_agent(A.alpha + il);
-        const int yu = A.y[iu] > 0 ? 1 : -1;
-        const int yl = A.y[il] > 0 ? 1 : -1;
-        if (LAY == LAY_DENSE) {
-            const float* xu = A.x + (size_t)iu * A.dpad;
-            const float* xl = A.x + (size_t)il * A.dpad;
-            for (int k = tid; k < A.dpad; k += BLOCK) pairv[k] = make_float2(xu[k], xl[k]);
-            __syncthreads();
-            if (tid == 0) {
-                double s;
-                if constexpr (std::is_same<KT, double>::value) {
-#pragma clang fp contract(off)
-                    double a = 0.0;
-                    for (int k = 0; k < A.dpad; ++k) {
-                        double t = (double)pairv[k].x - (double)pairv[k].y;
-                        a = a + t * t;
-                    }
-                    s = a;
-                } else {
-                    float a = 0.f;
-                    for (int k = 0; k < A.dpad; ++k) {
-                        float t = pairv[k].x - pairv[k].y;
-                        a = fmaf(t, t, a);
-                    }
-                    s = (double)a;
-                }
-                s_pair[0] = (double)kexp((KT)(-(KT)A.gamma * (KT)s));
-            }
-        } else {
-            const int pu0 = A.row_ptr[iu], pu1 = A.row_ptr[iu + 1];
-            const int pl0 = A.row_ptr[il], pl1 = A.row_ptr[il + 1];
-            const int nu = pu1 - pu0, nl = pl1 - pl0;
-            const int pn = s_prev_n;
-            // clear the previous pair
-            if (LAY == LAY_CSR_TABLE) {
-                for (int j = tid; j < pn; j += BLOCK) pairv[prev_cols[j]] = make_float2(0.f, 0.f);
-            } else {
-                for (int j = tid; j < pn; j += BLOCK) slot[prev_cols[j]] = 0;
-            }
-            __syncthreads();
-            float* pf = reinterpret_cast<float*>(pairv);
-            if (LAY == LAY_CSR_TABLE) {
-                for (int p = tid; p < nu; p += BLOCK) {
-                    int c = A.col[pu0 + p];
-                    pf[2 * c] = A.pattern_only ? 1.f : A.val[pu0 + p];
-                    prev_cols[p] = c;
-                }
-                for (int p = tid; p < nl; p += BLOCK) {
-                    int c = A.col[pl0 + p];
-                    pf[2 * c + 1] = A.pattern_only ? 1.f : A.val[pl0 + p];
-                    prev_cols[nu + p] = c;
-                }
-            } else {
-                for (int p = tid; p < nu; p += BLOCK) {
-                    int c = A.col[pu0 + p];
-                    slot[c] = (uint16_t)(1 + p);
-                    pairv[1 + p] = make_float2(A.pattern_only ? 1.f : A.val[pu0 + p], 0.f);
-                    prev_cols[p] = c;
-                }
-                __syncthreads();
-                for (int p = tid; p < nl; p += BLOCK) {
-                    int c = A.col[pl0 + p];
-                    float v = A.pattern_only ? 1.f : A.val[pl0 + p];
-                    int sl = slot[c];
-                    if (sl) {
-                        pf[2 * sl + 1] = v;
-                    } else {
-                        slot[c] = (uint16_t)(1 + nu + p);
-                        pairv[1 + nu + p] = make_float2(0.f, v);
-                    }
-                    prev_cols[nu + p] = c;
-                }
-            }
-            __syncthreads();
-            if (tid == 0) s_prev_n = nu + nl;
-            if (wid == 0) {
-                KT su = 0, sl2 = 0, dot = 0;
-                for (int p = lane; p < nu; p += 64) {
-                    KT v = A.pattern_only ? (KT)1 : (KT)A.val[pu0 + p];
-                    su += v * v;
-                }
-                for (int p = lane; p < nl; p += 64) {
-                    int c = A.col[pl0 + p];
-                    KT v = A.pattern_only ? (KT)1 : (KT)A.val[pl0 + p];
-                    float uv = (LAY == LAY_CSR_TABLE) ? pairv[c].x : pairv[slot[c]].x;
-                    sl2 += v * v;
-                    dot += v * (KT)uv;
-                }
-                su = wave_sum(su);
-                sl2 = wave_sum(sl2);
-                dot = wave_sum(dot);
-                if (lane == 0) {
-                    KT d2 = su + sl2 - (KT)2 * dot;
-                    if (d2 < (KT)0) d2 = (KT)0;
-                    s_pair[0] = (double)kexp((KT)(-(KT)A.gamma * d2));
-                    s_pair[1] = (double)su;
-                    s_pair[2] = (double)sl2;
-                }
-            }
-        }
-        __syncthreads();
-        const PairNew pn = pair_update(au, al, yu, yl, bu, bl, s_pair[0], C);
-        const KT gam = (KT)A.gamma;
-        const KT nuu = (KT)s_pair[1], nll = (KT)s_pair[2];
-
-        bool do_shrink = false;
-        if (A.H > 0) {
-            --counter;
-            do_shrink = counter == 0;
-        }
-
-        // ---- f update over this workgroup's active rows, selection candidates, shrink rule
-        double cbu = INFINITY, cbl = -INFINITY;
-        int ciu = IDX_NONE, cil = IDX_NONE;
-        int newcount = 0;
-        work_rows += (unsigned long long)nrows;
-        for (int base = 0; base < nrows; base += NG) {
-            const int t = base + g;
-            const bool valid = t < nrows;
-            const int i = valid ? lst[t] : 0;
-            bool keep = false;
-            if (valid) {
-                KT du2, dl2;
-                if (LAY == LAY_DENSE) {
-                    dense_dist<KT>(A.x + (size_t)i * A.dpad, pairv, A.dpad, du2, dl2);
-                } else {
-                    const int p0 = A.row_ptr[i], p1 = A.row_ptr[i + 1];
-                    if (gl == 0) work_nnz += (unsigned long long)(p1 - p0);
-                    KT nn = 0, su = 0, sl2 = 0;
-                    for (int p = p0 + gl; p < p1; p += LPR) {
-                        const int c = A.col[p];
-                        const KT v = A.pattern_only ? (KT)1 : (KT)A.val[p];
-                        const float2 ul = (LAY == LAY_CSR_TABLE) ? pairv[c] : pairv[slot[c]];
-                        nn += v * v;
-                        su += v * (KT)ul.x;
-                        sl2 += v * (KT)ul.y;
-                    }
-#pragma unroll
-                    for (int off = LPR / 2; off > 0; off >>= 1) {
-                        nn += __shfl_xor(nn, off);
-                        su += __shfl_xor(su, off);
-                        sl2 += __shfl_xor(sl2, off);
-                    }
-                    du2 = nn + nuu - (KT)2 * su;
-                    dl2 = nn + nll - (KT)2 * sl2;
-                    if (du2 < (KT)0) du2 = (KT)0;
-                    if (dl2 < (KT)0) dl2 = (KT)0;
-                }
-                if (gl == 0) {
-                    double ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2);
-                    double kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2);
-                    double fi;
-                    {
-#pragma clang fp contract(off)
-                        fi = A.f[i] + (pn.cu * ku + pn.cl * kl);
-                    }
-                    A.f[i] = fi;
-                    uint8_t st = A.status[i];
-                    if (i == iu) {
-                        st = st_make(yu > 0, pn.au, C);
-                        A.status[i] = st;
-                        st_agent(A.alpha + i, pn.au);
-                    } else if (i == il) {
-                        st = st_make(yl > 0, pn.al, C);
-                        A.status[i] = st;
-                        st_agent(A.alpha + i, pn.al);
-                    }
-                    keep = !(do_shrink && shrink_rule(st, fi, bu, bl));
-                    if (keep) {
-                        if (st_in_up(st) && better_up(fi, i, cbu, ciu)) { cbu = fi; ciu = i; }
-                        if (st_in_low(st) && better_low(fi, i, cbl, cil)) { cbl = fi; cil = i; }
-                    }
-                }
-            }
-            if (do_shrink) {   // stable in-place compaction of this chunk of the active list
-                const unsigned long long m = __ballot(keep);
-                const int wpre = __popcll(m & ((1ull << lane) - 1ull));
-                if (lane == 0) s_wc[wid] = __popcll(m);
-                __syncthreads();
-                int off = 0, tot = 0;
-                for (int w = 0; w < NW; ++w) {
-                    int c = s_wc[w];
-                    off += (w < wid) ? c : 0;
-                    tot += c;
-                }
-                if (keep) lst[newcount + off + wpre] = i;
-                newcount += tot;
-                __syncthreads();
-            }
-        }
-        if (do_shrink) nrows = newcount;
-
-        block_reduce_sel<BLOCK>(cbu, ciu, cbl, cil, s_v, s_i);
-        // ---- merge the workgroups' records (the paper's Allreduce of the b's)
-        if (G > 1) {
-            const int par = (int)(iter & 1);
-            if (tid == 0) {
-                Rec* r = A.rec + par * G + blk;
-                st_agent(&r->w[0], (unsigned long long)__double_as_longlong(cbu));
-                st_agent(&r->w[1], (unsigned long long)__double_as_longlong(cbl));
-                st_agent(&r->w[2], (unsigned long long)(unsigned)ciu | ((unsigned long long)(unsigned)cil << 32));
-                st_agent(&r->w[3], (unsigned long long)(unsigned)nrows);
-            }
-            bar_target += (unsigned long long)G;
-            if (!grid_barrier(A.bar, bar_target, &ctl->abort, A.spin_limit, &s_flag)) {
-                exit_reason = EXIT_ABORT;
-                break;
-            }
-            double rbu = INFINITY, rbl = -INFINITY;
-            int riu = IDX_NONE, ril = IDX_NONE;
-            long long rcnt = 0;
-            if (tid < G) {
-                const Rec* r = A.rec + par * G + tid;
-                rbu = __longlong_as_double((long long)ld_agent(&r->w[0]));
-                rbl = __longlong_as_double((long long)ld_agent(&r->w[1]));
-                unsigned long long w2 = ld_agent(&r->w[2]);
-                riu = (int)(unsigned)(w2 & 0xffffffffull);
-                ril = (int)(unsigned)(w2 >> 32);
-                rcnt = (long long)ld_agent(&r->w[3]);
-            }
-            if (do_shrink) {
-                long long c = wave_sum(rcnt);
-                if (lane == 0) s_wc[wid] = (int)c;
-            }
-            block_reduce_sel<BLOCK>(rbu, riu, rbl, ril, s_v, s_i);
-            if (tid == 0) {
-                s_sel[0] = rbu; s_sel[1] = rbl; s_seli[0] = riu; s_seli[1] = ril;
-                if (do_shrink) {
-                    long long c = 0;
-                    for (int w = 0; w < NW; ++w) c += s_wc[w];
-                    s_seli[2] = (int)c;
-                }
-            }
-        } else {
-            if (tid == 0) {
-                s_sel[0] = cbu; s_sel[1] = cbl; s_seli[0] = ciu; s_seli[1] = cil;
-                s_seli[2] = nrows;
-            }
-        }
-        __syncthreads();
-        bu = s_sel[0];
-        bl = s_sel[1];
-        iu = s_seli[0] == IDX_NONE ? -1 : s_seli[0];
-        il = s_seli[1] == IDX_NONE ? -1 : s_seli[1];
-        if (do_shrink) {
-            const long long tot = s_seli[2];
-            shrunk += n_act_total - tot;
-            n_act_total = tot;
-            ++passes;
-            counter = tot < A.H ? tot : A.H;
-            if (counter < 1) counter = 1;
-        }
-        ++iter;
-        __syncthreads();
-    }
-
-    if (tid == 0) A.cnt[blk] = nrows;
-    if (A.work) {
-        unsigned long long wn = wave_sum(work_nnz);
-        __syncthreads();
-        if (lane == 0) s_v[wid] = __longlong_as_double((long long)wn);
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long t = 0;
-            for (int w = 0; w < NW; ++w) t += (unsigned long long)__double_as_longlong(s_v[w]);
-            A.work[2 * blk] = work_rows;
-            A.work[2 * blk + 1] = t;
-        }
-    }
-    if (blk == 0 && tid == 0) {
-        ctl->b_up = bu; ctl->b_low = bl; ctl->i_up = iu; ctl->i_low = il;
-        ctl->iter = iter; ctl->counter = counter; ctl->n_active = n_act_total;
-        ctl->shrink_passes = passes; ctl->shrunk_total = shrunk;
-        ctl->exit_reason = exit_reason;
-    }
-}
-
-template <int LAY, typename KT, int LPR>
-static hipError_t launch_loop_t(const StepArgs& a, int G, size_t lds, hipStream_t s) {
-    auto fn = smo_loop_kernel<LAY, KT, LPR>;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    StepArgs copy = a;
-    void* args[] = {&copy};
-    return hipLaunchCooperativeKernel((const void*)fn, dim3(G), dim3(STEP_BLOCK), args, (unsigned)lds, s);
-}
-
-size_t step_lds_bytes(int lay, int d, int dpad, int max_row_nnz) {
-    if (lay == LAY_DENSE) return sizeof(float2) * (size_t)dpad;
-    if (lay == LAY_CSR_TABLE) return sizeof(float2) * (size_t)d + sizeof(int) * 2 * (size_t)max_row_nnz;
-    size_t nv = 1 + 2 * (size_t)max_row_nnz;
-    return sizeof(float2) * nv + ((sizeof(uint16_t) * (size_t)d + 15) & ~(size_t)15) + sizeof(int) * 2 * (size_t)max_row_nnz;
-}
-
-template <int LAY, typename KT>
-static hipError_t dispatch_lpr(const StepArgs& a, int G, int lpr, size_t lds, hipStream_t s) {
-    if constexpr (LAY == LAY_DENSE) return launch_loop_t<LAY, KT, 1>(a, G, lds, s);
-    else switch (lpr) {
-        case 1: return launch_loop_t<LAY, KT, 1>(a, G, lds, s);
-        case 2: return launch_loop_t<LAY, KT, 2>(a, G, lds, s);
-        case 4: return launch_loop_t<LAY, KT, 4>(a, G, lds, s);
-        case 8: return launch_loop_t<LAY, KT, 8>(a, G, lds, s);
-        case 16: return launch_loop_t<LAY, KT, 16>(a, G, lds, s);
-        case 32: return launch_loop_t<LAY, KT, 32>(a, G, lds, s);
-        default: return launch_loop_t<LAY, KT, 64>(a, G, lds, s);
-    }
-}
-
-hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, hipStream_t s) {
-    size_t lds = step_lds_bytes(a.lay, a.d, a.dpad, a.max_row_nnz);
-    if (kprec == SVM_KERNEL_FP64) {
-        if (a.lay == LAY_DENSE) return dispatch_lpr<LAY_DENSE, double>(a, G, lpr, lds, s);
-        if (a.lay == LAY_CSR_TABLE) return dispatch_lpr<LAY_CSR_TABLE, double>(a, G, lpr, lds, s);
-        return dispatch_lpr<LAY_CSR_SLOT, double>(a, G, lpr, lds, s);
-    }
-    if (a.lay == LAY_DENSE) return dispatch_lpr<LAY_DENSE, float>(a, G, lpr, lds, s);
-    if (a.lay == LAY_CSR_TABLE) return dispatch_lpr<LAY_CSR_TABLE, float>(a, G, lpr, lds, s);
-    return dispatch_lpr<LAY_CSR_SLOT, float>(a, G, lpr, lds, s);
-}
-
-template <int LAY, typename KT, int LPR>
-static int max_blocks_t(size_t lds) {
-    int nb = 0;
-    auto fn = smo_loop_kernel<LAY, KT, LPR>;
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, STEP_BLOCK, lds) != hipSuccess) return 0;
-    return nb;
-}
-
-template <int LAY, typename KT>
-static int max_blocks_lpr(int lpr, size_t lds) {
-    if constexpr (LAY == LAY_DENSE) return max_blocks_t<LAY, KT, 1>(lds);
-    else switch (lpr) {
-        case 1: return max_blocks_t<LAY, KT, 1>(lds);
-        case 2: return max_blocks_t<LAY, KT, 2>(lds);
-        case 4: return max_blocks_t<LAY, KT, 4>(lds);
-        case 8: return max_blocks_t<LAY, KT, 8>(lds);
-        case 16: return max_blocks_t<LAY, KT, 16>(lds);
-        case 32: return max_blocks_t<LAY, KT, 32>(lds);
-        default: return max_blocks_t<LAY, KT, 64>(lds);
-    }
-}
-
-int step_max_blocks(int lay, int lpr, int kprec, size_t lds) {
-    int per_cu;
-    if (kprec == SVM_KERNEL_FP64) {
-        per_cu = lay == LAY_DENSE ? max_blocks_lpr<LAY_DENSE, double>(lpr, lds)
-               : lay == LAY_CSR_TABLE ? max_blocks_lpr<LAY_CSR_TABLE, double>(lpr, lds)
-                                      : max_blocks_lpr<LAY_CSR_SLOT, double>(lpr, lds);
-    } else {
-        per_cu = lay == LAY_DENSE ? max_blocks_lpr<LAY_DENSE, float>(lpr, lds)
-               : lay == LAY_CSR_TABLE ? max_blocks_lpr<LAY_CSR_TABLE, float>(lpr, lds)
-                                      : max_blocks_lpr<LAY_CSR_SLOT, float>(lpr, lds);
-    }
-    return per_cu * device_cu_count();
-}
 
 int device_cu_count() {
     int dev = 0, cus = 0;
@@ -792,7 +178,7 @@ __global__ __launch_bounds__(256) void select_partial_kernel(const int32_t* seg_
     }
 }
 
-__global__ __launch_bounds__(1024) void select_merge_kernel(int G, const Rec* rec, Ctl* ctl) {
+__global__ __launch_bounds__(1024) void select_merge_kernel(int G, const Rec* rec, const double* alpha, Ctl* ctl) {
     __shared__ double s_v[32];
     __shared__ int s_i[32];
     __shared__ long long s_c[16];
@@ -817,6 +203,8 @@ __global__ __launch_bounds__(1024) void select_merge_kernel(int G, const Rec* re
         ctl->b_up = bu; ctl->b_low = bl;
         ctl->i_up = iu == IDX_NONE ? -1 : iu;
         ctl->i_low = il == IDX_NONE ? -1 : il;
+        ctl->a_up = iu == IDX_NONE ? 0.0 : alpha[iu];
+        ctl->a_low = il == IDX_NONE ? 0.0 : alpha[il];
         ctl->n_active = tot;
     }
 }
@@ -826,7 +214,7 @@ hipError_t launch_select(int G, const int32_t* seg_start, const int32_t* cnt, co
     select_partial_kernel<<<G, 256, 0, s>>>(seg_start, cnt, act, f, alpha, y, C, rec);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    select_merge_kernel<<<1, 1024, 0, s>>>(G, rec, ctl);
+    select_merge_kernel<<<1, 1024, 0, s>>>(G, rec, alpha, ctl);
     return hipGetLastError();
 }
 

@@ -1,0 +1,643 @@
+// svm_step.hip -- the persistent SMO loop of libsvmhip.so for gfx950.
+//
+// One cooperative launch runs the inner loop of Alg. 5 (Alg. 2 when shrinking
+// is off) until the gap b_low - b_up drops to the phase tolerance or the
+// iteration cap is reached.  Every iteration:
+//   1. each workgroup stages the working pair (x_up, x_low) in LDS -- the
+//      paper's broadcast -- and computes the FP64 pair update (eq:alphaup /
+//      eq:rho) redundantly, as every MPI rank does;
+//   2. it updates f (eq:fup) over the active rows of its segment, applies the
+//      shrink rule (eq:shrink) on shrink iterations and compacts its active
+//      list in place (Alg. 4), and reduces the two-threshold candidates
+//      (eq:bminmax, lowest sample id on ties);
+//   3. the workgroups publish one record each and meet at a grid barrier --
+//      the paper's Allreduce -- after which every workgroup merges all
+//      records and holds the next pair.
+// A workgroup owns a fixed segment of the samples for the whole launch and,
+// when it fits, keeps the segment's per-row state (f, status, active list,
+// CSR offsets) and even its row payload in LDS, so an iteration reads HBM
+// only for the working pair and the records.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "svm_device.h"
+#include "svm_internal.h"
+
+namespace svm {
+
+static size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, long long nnz_seg_max,
+                      bool pattern_only, int max_mode) {
+    StepLds p{};
+    if (lay == LAY_DENSE) p.pair_bytes = sizeof(float2) * (size_t)dpad;
+    else if (lay == LAY_CSR_TABLE) p.pair_bytes = sizeof(float2) * (size_t)d + sizeof(int) * 2 * (size_t)max_row_nnz;
+    else
+        p.pair_bytes = sizeof(float2) * (1 + 2 * (size_t)max_row_nnz) + al16(sizeof(uint16_t) * (size_t)d) +
+                       sizeof(int) * 2 * (size_t)max_row_nnz;
+    const bool csr = lay != LAY_DENSE;
+    p.meta_off = al16(p.pair_bytes);
+    const size_t meta = al16(2 * sizeof(double) * (size_t)nseg_max + sizeof(int) * (size_t)nseg_max +
+                             (csr ? sizeof(int) * ((size_t)nseg_max + 1) : 0) + (size_t)nseg_max);
+    p.pay_off = p.meta_off + meta;
+    size_t pay;
+    if (csr) pay = al16(sizeof(uint16_t) * (size_t)nnz_seg_max) + (pattern_only ? 0 : sizeof(float) * (size_t)nnz_seg_max);
+    else pay = sizeof(float) * (size_t)dpad * (size_t)nseg_max;
+    if (max_mode >= STEP_LDS_ALL && (!csr || d <= 65536) && p.pay_off + pay <= STEP_LDS_BUDGET) {
+        p.mode = STEP_LDS_ALL;
+        p.total = p.pay_off + pay;
+    } else if (max_mode >= STEP_LDS_STATE && p.pay_off <= STEP_LDS_BUDGET) {
+        p.mode = STEP_LDS_STATE;
+        p.total = p.pay_off;
+    } else {
+        p.mode = STEP_GLOBAL;
+        p.total = p.pair_bytes;
+    }
+    return p;
+}
+
+template <int LAY, typename KT, int LPR, int MODE>
+__global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
+    constexpr int BLOCK = STEP_BLOCK;
+    constexpr int NW = BLOCK / 64;
+    constexpr int NG = BLOCK / LPR;
+    constexpr bool CSR = LAY != LAY_DENSE;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double s_v[4 * NW];
+    __shared__ int s_i[2 * NW];
+    __shared__ int s_wc[NW];
+    __shared__ double s_pair[4];     // K_ul, |u|^2, |l|^2
+    __shared__ double s_sel[4];
+    __shared__ int s_seli[3];
+    __shared__ int s_prev_n;
+    __shared__ unsigned long long s_ext[2];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int g = tid / LPR, gl = tid % LPR;
+    const int blk = blockIdx.x, G = gridDim.x;
+    const double C = A.C;
+
+    // ---- LDS: the working pair first
+    float2* pairv = reinterpret_cast<float2*>(smem);
+    uint16_t* slot = nullptr;
+    int* prev_cols = nullptr;
+    if (LAY == LAY_CSR_TABLE) {
+        prev_cols = reinterpret_cast<int*>(smem + sizeof(float2) * (size_t)A.d);
+        for (int k = tid; k < A.d; k += BLOCK) pairv[k] = make_float2(0.f, 0.f);
+    } else if (LAY == LAY_CSR_SLOT) {
+        const int nv = 1 + 2 * A.max_row_nnz;
+        slot = reinterpret_cast<uint16_t*>(smem + sizeof(float2) * (size_t)nv);
+        prev_cols = reinterpret_cast<int*>(smem + sizeof(float2) * (size_t)nv + ((sizeof(uint16_t) * (size_t)A.d + 15) & ~(size_t)15));
+        for (int k = tid; k < A.d; k += BLOCK) slot[k] = 0;
+        if (tid == 0) pairv[0] = make_float2(0.f, 0.f);
+    }
+    if (tid == 0) s_prev_n = 0;
+
+    // ---- this workgroup's segment and where its rows live during the launch
+    const int seg0 = A.seg_start[blk];
+    const int nseg = A.seg_start[blk + 1] - seg0;
+    int nrows = A.cnt[blk];
+    const int gbase = CSR ? A.row_ptr[seg0] : 0;
+    double* F;
+    double* AL = nullptr;   // alpha of the segment's rows (LDS modes)
+    uint8_t* ST;
+    int* L;           // active list: global ids (STEP_GLOBAL) or segment-local indices
+    int* OFF = nullptr;
+    float* XL = nullptr;
+    uint16_t* COLL = nullptr;
+    float* VALL = nullptr;
+    if constexpr (MODE == STEP_GLOBAL) {
+        F = A.f + seg0;
+        ST = A.status + seg0;
+        L = A.act + seg0;
+    } else {
+        F = reinterpret_cast<double*>(smem + A.lds_meta_off);
+        AL = F + A.nseg_max;
+        L = reinterpret_cast<int*>(AL + A.nseg_max);
+        OFF = L + A.nseg_max;
+        ST = reinterpret_cast<uint8_t*>(OFF + (CSR ? A.nseg_max + 1 : 0));
+        for (int li = tid; li < nseg; li += BLOCK) {
+            F[li] = A.f[seg0 + li];
+            AL[li] = A.alpha[seg0 + li];
+            ST[li] = A.status[seg0 + li];
+        }
+        for (int t = tid; t < nrows; t += BLOCK) L[t] = A.act[seg0 + t] - seg0;
+        if (CSR)
+            for (int li = tid; li <= nseg; li += BLOCK) OFF[li] = A.row_ptr[seg0 + li] - gbase;
+        if constexpr (MODE == STEP_LDS_ALL) {
+            if (CSR) {
+                const int nnz = A.row_ptr[seg0 + nseg] - gbase;
+                COLL = reinterpret_cast<uint16_t*>(smem + A.lds_pay_off);
+                VALL = reinterpret_cast<float*>(smem + A.lds_pay_off + ((sizeof(uint16_t) * (size_t)A.nnz_seg_max + 15) & ~(size_t)15));
+                for (int p = tid; p < nnz; p += BLOCK) {
+                    COLL[p] = (uint16_t)A.col[gbase + p];
+                    if (!A.pattern_only) VALL[p] = A.val[gbase + p];
+                }
+            } else {
+                XL = reinterpret_cast<float*>(smem + A.lds_pay_off);
+                const float4* src = reinterpret_cast<const float4*>(A.x + (size_t)seg0 * A.dpad);
+                float4* dst = reinterpret_cast<float4*>(XL);
+                const int n4 = nseg * A.dpad / 4;
+                for (int e = tid; e < n4; e += BLOCK) dst[e] = src[e];
+            }
+        }
+    }
+
+    // ---- solver state (identical in every workgroup)
+    Ctl* ctl = A.ctl;
+    double bu = ctl->b_up, bl = ctl->b_low;
+    double au = ctl->a_up, al = ctl->a_low;
+    int iu = ctl->i_up, il = ctl->i_low;
+    unsigned long long ext_u = 0, ext_l = 0;   // CSR extents of the pair rows (0: read row_ptr)
+    long long iter = ctl->iter, counter = ctl->counter, n_act_total = ctl->n_active;
+    long long passes = ctl->shrink_passes, shrunk = ctl->shrunk_total;
+    int exit_reason = EXIT_NONE;
+    unsigned long long work_rows = 0, work_nnz = 0;
+    // per-phase timer of workgroup 0, kept in LDS so it costs no registers
+    __shared__ unsigned long long s_pt[PROF_SLOTS + 1];
+    const bool prof_on = A.prof != nullptr && blk == 0 && tid == 0;
+    if (prof_on) {
+        for (int k = 0; k < PROF_SLOTS; ++k) s_pt[k] = 0;
+        s_pt[PROF_SLOTS] = wall_clock64();
+    }
+    auto lap = [&](int k) {
+        if (prof_on) {
+            const unsigned long long t = wall_clock64();
+            s_pt[k] += t - s_pt[PROF_SLOTS];
+            s_pt[PROF_SLOTS] = t;
+        }
+    };
+    __syncthreads();
+    lap(6);
+
+    for (;;) {
+        if (!(bl - bu > A.thr)) { exit_reason = EXIT_CONVERGED; break; }
+        if (iter >= A.max_iter) { exit_reason = EXIT_MAXITER; break; }
+        if (blk == 0 && tid == 0 && iter < A.trace_cap) {
+            A.tr_iu[iter] = iu; A.tr_il[iter] = il; A.tr_bu[iter] = bu; A.tr_bl[iter] = bl;
+        }
+        // ---- 1. the working pair: labels, rows into LDS (alpha came with the records)
+        const int yu = A.y[iu] > 0 ? 1 : -1;
+        const int yl = A.y[il] > 0 ? 1 : -1;
+        if (LAY == LAY_DENSE) {
+            const float* xu = A.x + (size_t)iu * A.dpad;
+            const float* xl = A.x + (size_t)il * A.dpad;
+            for (int k = tid; k < A.dpad; k += BLOCK) pairv[k] = make_float2(xu[k], xl[k]);
+            __syncthreads();
+            if constexpr (std::is_same<KT, double>::value) {
+                // sequential in k: the same rounding as the FP64 reference
+                if (tid == 0) {
+#pragma clang fp contract(off)
+                    double a = 0.0;
+                    for (int k = 0; k < A.dpad; ++k) {
+                        double t = (double)pairv[k].x - (double)pairv[k].y;
+                        a = a + t * t;
+                    }
+                    s_pair[0] = exp(-A.gamma * a);
+                }
+            } else {
+                if (wid == 0) {
+                    float a = 0.f;
+                    for (int k = lane; k < A.dpad; k += 64) {
+                        float t = pairv[k].x - pairv[k].y;
+                        a = fmaf(t, t, a);
+                    }
+                    a = wave_sum(a);
+                    if (lane == 0) s_pair[0] = (double)expf(-(float)A.gamma * a);
+                }
+            }
+        } else {
+            int pu0, pu1, pl0, pl1;
+            if (ext_u) { pu0 = (int)(unsigned)(ext_u & 0xffffffffull); pu1 = (int)(unsigned)(ext_u >> 32); }
+            else { pu0 = A.row_ptr[iu]; pu1 = A.row_ptr[iu + 1]; }
+            if (ext_l) { pl0 = (int)(unsigned)(ext_l & 0xffffffffull); pl1 = (int)(unsigned)(ext_l >> 32); }
+            else { pl0 = A.row_ptr[il]; pl1 = A.row_ptr[il + 1]; }
+            const int nu = pu1 - pu0, nl = pl1 - pl0;
+            const int npv = s_prev_n;
+            if (LAY == LAY_CSR_TABLE) {
+                for (int j = tid; j < npv; j += BLOCK) pairv[prev_cols[j]] = make_float2(0.f, 0.f);
+            } else {
+                for (int j = tid; j < npv; j += BLOCK) slot[prev_cols[j]] = 0;
+            }
+            __syncthreads();
+            float* pf = reinterpret_cast<float*>(pairv);
+            if (LAY == LAY_CSR_TABLE) {
+                for (int p = tid; p < nu; p += BLOCK) {
+                    int c = A.col[pu0 + p];
+                    pf[2 * c] = A.pattern_only ? 1.f : A.val[pu0 + p];
+                    prev_cols[p] = c;
+                }
+                for (int p = tid; p < nl; p += BLOCK) {
+                    int c = A.col[pl0 + p];
+                    pf[2 * c + 1] = A.pattern_only ? 1.f : A.val[pl0 + p];
+                    prev_cols[nu + p] = c;
+                }
+            } else {
+                for (int p = tid; p < nu; p += BLOCK) {
+                    int c = A.col[pu0 + p];
+                    slot[c] = (uint16_t)(1 + p);
+                    pairv[1 + p] = make_float2(A.pattern_only ? 1.f : A.val[pu0 + p], 0.f);
+                    prev_cols[p] = c;
+                }
+                __syncthreads();
+                for (int p = tid; p < nl; p += BLOCK) {
+                    int c = A.col[pl0 + p];
+                    float v = A.pattern_only ? 1.f : A.val[pl0 + p];
+                    int sl = slot[c];
+                    if (sl) {
+                        pf[2 * sl + 1] = v;
+                    } else {
+                        slot[c] = (uint16_t)(1 + nu + p);
+                        pairv[1 + nu + p] = make_float2(0.f, v);
+                    }
+                    prev_cols[nu + p] = c;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) s_prev_n = nu + nl;
+            if (wid == 0) {
+                KT su = 0, sl2 = 0, dot = 0;
+                for (int p = lane; p < nu; p += 64) {
+                    KT v = A.pattern_only ? (KT)1 : (KT)A.val[pu0 + p];
+                    su += v * v;
+                }
+                for (int p = lane; p < nl; p += 64) {
+                    int c = A.col[pl0 + p];
+                    KT v = A.pattern_only ? (KT)1 : (KT)A.val[pl0 + p];
+                    float uv = (LAY == LAY_CSR_TABLE) ? pairv[c].x : pairv[slot[c]].x;
+                    sl2 += v * v;
+                    dot += v * (KT)uv;
+                }
+                su = wave_sum(su);
+                sl2 = wave_sum(sl2);
+                dot = wave_sum(dot);
+                if (lane == 0) {
+                    KT d2 = su + sl2 - (KT)2 * dot;
+                    if (d2 < (KT)0) d2 = (KT)0;
+                    s_pair[0] = (double)kexp((KT)(-(KT)A.gamma * d2));
+                    s_pair[1] = (double)su;
+                    s_pair[2] = (double)sl2;
+                }
+            }
+        }
+        __syncthreads();
+        const PairNew pn = pair_update(au, al, yu, yl, bu, bl, s_pair[0], C);
+        const KT gam = (KT)A.gamma;
+        const KT nuu = CSR ? (KT)s_pair[1] : (KT)0, nll = CSR ? (KT)s_pair[2] : (KT)0;
+
+        bool do_shrink = false;
+        if (A.H > 0) {
+            --counter;
+            do_shrink = counter == 0;
+        }
+        lap(0);
+
+        // ---- 2. f update over the active rows of this segment, candidates, shrink rule
+        double cbu = INFINITY, cbl = -INFINITY;
+        int ciu = IDX_NONE, cil = IDX_NONE;
+        int newcount = 0;
+        work_rows += (unsigned long long)nrows;
+        for (int base = 0; base < nrows; base += NG) {
+            const int t = base + g;
+            const bool valid = t < nrows;
+            const int li = valid ? (MODE == STEP_GLOBAL ? L[t] - seg0 : L[t]) : 0;
+            const int i = seg0 + li;
+            bool keep = false;
+            if (valid) {
+                KT du2, dl2;
+                if constexpr (LAY == LAY_DENSE) {
+                    const float* xr = (MODE == STEP_LDS_ALL) ? XL + (size_t)li * A.dpad : A.x + (size_t)i * A.dpad;
+                    dense_dist<KT>(xr, pairv, A.dpad, du2, dl2);
+                } else {
+                    int p0, p1;
+                    if constexpr (MODE == STEP_GLOBAL) {
+                        p0 = A.row_ptr[i] - gbase;
+                        p1 = A.row_ptr[i + 1] - gbase;
+                    } else {
+                        p0 = OFF[li];
+                        p1 = OFF[li + 1];
+                    }
+                    if (gl == 0) work_nnz += (unsigned long long)(p1 - p0);
+                    KT nn = 0, su = 0, sl2 = 0;
+                    for (int p = p0 + gl; p < p1; p += LPR) {
+                        int c;
+                        KT v;
+                        if constexpr (MODE == STEP_LDS_ALL) {
+                            c = COLL[p];
+                            v = A.pattern_only ? (KT)1 : (KT)VALL[p];
+                        } else {
+                            c = A.col[gbase + p];
+                            v = A.pattern_only ? (KT)1 : (KT)A.val[gbase + p];
+                        }
+                        const float2 ul = (LAY == LAY_CSR_TABLE) ? pairv[c] : pairv[slot[c]];
+                        nn += v * v;
+                        su += v * (KT)ul.x;
+                        sl2 += v * (KT)ul.y;
+                    }
+#pragma unroll
+                    for (int off = LPR / 2; off > 0; off >>= 1) {
+                        nn += __shfl_xor(nn, off);
+                        su += __shfl_xor(su, off);
+                        sl2 += __shfl_xor(sl2, off);
+                    }
+                    du2 = nn + nuu - (KT)2 * su;
+                    dl2 = nn + nll - (KT)2 * sl2;
+                    if (du2 < (KT)0) du2 = (KT)0;
+                    if (dl2 < (KT)0) dl2 = (KT)0;
+                }
+                if (gl == 0) {
+                    const double ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2);
+                    const double kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2);
+                    double fi;
+                    {
+#pragma clang fp contract(off)
+                        fi = F[li] + (pn.cu * ku + pn.cl * kl);
+                    }
+                    F[li] = fi;
+                    uint8_t st = ST[li];
+                    if (i == iu) {
+                        st = st_make(yu > 0, pn.au, C);
+                        ST[li] = st;
+                        if constexpr (MODE == STEP_GLOBAL) st_agent(A.alpha + i, pn.au);
+                        else AL[li] = pn.au;
+                    } else if (i == il) {
+                        st = st_make(yl > 0, pn.al, C);
+                        ST[li] = st;
+                        if constexpr (MODE == STEP_GLOBAL) st_agent(A.alpha + i, pn.al);
+                        else AL[li] = pn.al;
+                    }
+                    keep = !(do_shrink && shrink_rule(st, fi, bu, bl));
+                    if (keep) {
+                        if (st_in_up(st) && better_up(fi, i, cbu, ciu)) { cbu = fi; ciu = i; }
+                        if (st_in_low(st) && better_low(fi, i, cbl, cil)) { cbl = fi; cil = i; }
+                    }
+                }
+            }
+            if (do_shrink) {   // stable in-place compaction of this chunk of the active list
+                const unsigned long long m = __ballot(keep);
+                const int wpre = __popcll(m & ((1ull << lane) - 1ull));
+                if (lane == 0) s_wc[wid] = __popcll(m);
+                __syncthreads();
+                int off = 0, tot = 0;
+                for (int w = 0; w < NW; ++w) {
+                    int c = s_wc[w];
+                    off += (w < wid) ? c : 0;
+                    tot += c;
+                }
+                if (keep) L[newcount + off + wpre] = (MODE == STEP_GLOBAL) ? i : li;
+                newcount += tot;
+                __syncthreads();
+            }
+        }
+        if (do_shrink) nrows = newcount;
+        lap(1);
+
+        block_reduce_sel_all<BLOCK>(cbu, ciu, cbl, cil, s_v, s_i);
+        // alpha and CSR extent of this workgroup's candidates: its own rows, which no other
+        // workgroup writes, so they travel in the records instead of being re-read later
+        double cau = 0.0, cal = 0.0;
+        unsigned long long ceu = 0, cel = 0;
+        if (tid == 0) {
+            if (ciu != IDX_NONE) {
+                if constexpr (MODE == STEP_GLOBAL) cau = ld_agent(A.alpha + ciu);
+                else cau = AL[ciu - seg0];
+                if constexpr (CSR) {
+                    unsigned p0, p1;
+                    if constexpr (MODE == STEP_GLOBAL) { p0 = (unsigned)A.row_ptr[ciu]; p1 = (unsigned)A.row_ptr[ciu + 1]; }
+                    else { p0 = (unsigned)(gbase + OFF[ciu - seg0]); p1 = (unsigned)(gbase + OFF[ciu - seg0 + 1]); }
+                    ceu = (unsigned long long)p0 | ((unsigned long long)p1 << 32);
+                }
+            }
+            if (cil != IDX_NONE) {
+                if constexpr (MODE == STEP_GLOBAL) cal = ld_agent(A.alpha + cil);
+                else cal = AL[cil - seg0];
+                if constexpr (CSR) {
+                    unsigned p0, p1;
+                    if constexpr (MODE == STEP_GLOBAL) { p0 = (unsigned)A.row_ptr[cil]; p1 = (unsigned)A.row_ptr[cil + 1]; }
+                    else { p0 = (unsigned)(gbase + OFF[cil - seg0]); p1 = (unsigned)(gbase + OFF[cil - seg0 + 1]); }
+                    cel = (unsigned long long)p0 | ((unsigned long long)p1 << 32);
+                }
+            }
+        }
+        // ---- 3. exchange (the paper's Allreduce of the b's): every workgroup stores its record
+        // as tag-validated words and reads everybody's record; no barrier, no fence, no atomic RMW
+        if (G > 1) {
+            const int par = (int)(iter & 1);
+            const unsigned tg = (unsigned)(iter + 1);
+            const unsigned long long TAG = (unsigned long long)tg << 32;
+            if (tid == 0) {
+                unsigned long long* w = A.rec[par * G + blk].w;
+                const unsigned long long bub = (unsigned long long)__double_as_longlong(cbu);
+                const unsigned long long blb = (unsigned long long)__double_as_longlong(cbl);
+                const unsigned long long aub = (unsigned long long)__double_as_longlong(cau);
+                const unsigned long long alb = (unsigned long long)__double_as_longlong(cal);
+                st_agent(w + 0, TAG | (bub & 0xffffffffull));
+                st_agent(w + 1, TAG | (bub >> 32));
+                st_agent(w + 2, TAG | (blb & 0xffffffffull));
+                st_agent(w + 3, TAG | (blb >> 32));
+                st_agent(w + 4, TAG | (unsigned)ciu);
+                st_agent(w + 5, TAG | (unsigned)cil);
+                st_agent(w + 6, TAG | (unsigned)nrows);
+                st_agent(w + 7, TAG | (aub & 0xffffffffull));
+                st_agent(w + 8, TAG | (aub >> 32));
+                st_agent(w + 9, TAG | (alb & 0xffffffffull));
+                st_agent(w + 10, TAG | (alb >> 32));
+                st_agent(w + 11, TAG | (ceu & 0xffffffffull));
+                st_agent(w + 12, TAG | (ceu >> 32));
+                st_agent(w + 13, TAG | (cel & 0xffffffffull));
+                st_agent(w + 14, TAG | (cel >> 32));
+            }
+            lap(2);
+            double rbu = INFINITY, rbl = -INFINITY, rau = 0.0, ral = 0.0;
+            int riu = IDX_NONE, ril = IDX_NONE;
+            unsigned long long reu = 0, rel = 0;
+            long long rcnt = 0;
+            int ab = 0;
+            if (tid < G) {
+                const unsigned long long* w = A.rec[par * G + tid].w;
+                unsigned v[REC_WORDS];
+                const unsigned long long t0 = wall_clock64();
+                // wait on the last word written first, then read the record
+                while ((unsigned)(ld_agent(w + REC_WORDS - 1) >> 32) != tg) {
+                    if (wall_clock64() - t0 > A.spin_limit) { ab = 1; break; }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                for (; !ab;) {
+                    bool ok = true;
+#pragma unroll
+                    for (int k = 0; k < REC_WORDS; ++k) {
+                        const unsigned long long x = ld_agent(w + k);
+                        v[k] = (unsigned)(x & 0xffffffffull);
+                        ok = ok && (unsigned)(x >> 32) == tg;
+                    }
+                    if (ok) break;
+                    if (wall_clock64() - t0 > A.spin_limit) { ab = 1; break; }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                rbu = __longlong_as_double((long long)(((unsigned long long)v[1] << 32) | v[0]));
+                rbl = __longlong_as_double((long long)(((unsigned long long)v[3] << 32) | v[2]));
+                riu = (int)v[4];
+                ril = (int)v[5];
+                rcnt = (long long)v[6];
+                rau = __longlong_as_double((long long)(((unsigned long long)v[8] << 32) | v[7]));
+                ral = __longlong_as_double((long long)(((unsigned long long)v[10] << 32) | v[9]));
+                reu = ((unsigned long long)v[12] << 32) | v[11];
+                rel = ((unsigned long long)v[14] << 32) | v[13];
+            }
+            if (__syncthreads_or(ab)) {
+                if (tid == 0) __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                exit_reason = EXIT_ABORT;
+                break;
+            }
+            lap(3);
+            if (do_shrink) {
+                const long long csum = wave_sum(rcnt);
+                if (lane == 0) s_wc[wid] = (int)csum;
+            }
+            // reduce (value, id) -- every thread ends with the winners -- and the record holding
+            // each winner publishes its payload (alpha, CSR extent)
+            const int myiu = riu, myil = ril;
+            block_reduce_sel_all<BLOCK>(rbu, riu, rbl, ril, s_v, s_i);
+            if (tid < G) {
+                if (myiu != IDX_NONE && myiu == riu) { s_sel[2] = rau; s_ext[0] = reu; }
+                if (myil != IDX_NONE && myil == ril) { s_sel[3] = ral; s_ext[1] = rel; }
+            }
+            if (tid == 0) {
+                s_sel[0] = rbu; s_sel[1] = rbl;
+                s_seli[0] = riu; s_seli[1] = ril;
+                if (do_shrink) {
+                    long long c = 0;
+                    for (int w = 0; w < NW; ++w) c += s_wc[w];
+                    s_seli[2] = (int)c;
+                }
+            }
+        } else {
+            if (tid == 0) {
+                s_sel[0] = cbu; s_sel[1] = cbl; s_sel[2] = cau; s_sel[3] = cal;
+                s_seli[0] = ciu; s_seli[1] = cil;
+                s_seli[2] = nrows;
+                s_ext[0] = ceu; s_ext[1] = cel;
+            }
+            lap(2);
+        }
+        __syncthreads();
+        bu = s_sel[0];
+        bl = s_sel[1];
+        au = s_sel[2];
+        al = s_sel[3];
+        ext_u = s_ext[0];
+        ext_l = s_ext[1];
+        iu = s_seli[0] == IDX_NONE ? -1 : s_seli[0];
+        il = s_seli[1] == IDX_NONE ? -1 : s_seli[1];
+        if (do_shrink) {
+            const long long tot = s_seli[2];
+            shrunk += n_act_total - tot;
+            n_act_total = tot;
+            ++passes;
+            counter = tot < A.H ? tot : A.H;
+            if (counter < 1) counter = 1;
+        }
+        ++iter;
+        lap(4);
+        if (prof_on) s_pt[5] += 1;
+    }
+
+    // ---- write the segment back for the host-side phases (reconstruction, selection)
+    if constexpr (MODE != STEP_GLOBAL) {
+        for (int li = tid; li < nseg; li += BLOCK) {
+            A.f[seg0 + li] = F[li];
+            A.alpha[seg0 + li] = AL[li];
+            A.status[seg0 + li] = ST[li];
+        }
+        for (int t = tid; t < nrows; t += BLOCK) A.act[seg0 + t] = seg0 + L[t];
+    }
+    if (tid == 0) A.cnt[blk] = nrows;
+    if (A.work) {
+        unsigned long long wn = wave_sum(work_nnz);
+        __syncthreads();
+        if (lane == 0) s_v[wid] = __longlong_as_double((long long)wn);
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < NW; ++w) t += (unsigned long long)__double_as_longlong(s_v[w]);
+            A.work[2 * blk] = work_rows;
+            A.work[2 * blk + 1] = t;
+        }
+    }
+    if (prof_on) {
+        lap(7);
+        for (int k = 0; k < PROF_SLOTS; ++k) A.prof[k] += s_pt[k];
+    }
+    if (blk == 0 && tid == 0) {
+        ctl->b_up = bu; ctl->b_low = bl; ctl->i_up = iu; ctl->i_low = il;
+        ctl->a_up = au; ctl->a_low = al;
+        ctl->iter = iter; ctl->counter = counter; ctl->n_active = n_act_total;
+        ctl->shrink_passes = passes; ctl->shrunk_total = shrunk;
+        ctl->exit_reason = exit_reason;
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+
+template <int LAY, typename KT, int LPR, int MODE>
+static const void* loop_fn() {
+    return (const void*)smo_loop_kernel<LAY, KT, LPR, MODE>;
+}
+
+template <int LAY, typename KT, int MODE>
+static const void* pick_lpr(int lpr) {
+    if constexpr (LAY == LAY_DENSE) {
+        return loop_fn<LAY, KT, 1, MODE>();
+    } else {
+        switch (lpr) {
+            case 1: return loop_fn<LAY, KT, 1, MODE>();
+            case 2: return loop_fn<LAY, KT, 2, MODE>();
+            case 4: return loop_fn<LAY, KT, 4, MODE>();
+            case 8: return loop_fn<LAY, KT, 8, MODE>();
+            case 16: return loop_fn<LAY, KT, 16, MODE>();
+            default: return loop_fn<LAY, KT, 32, MODE>();
+        }
+    }
+}
+
+template <int LAY, typename KT>
+static const void* pick_mode(int mode, int lpr) {
+    if (mode == STEP_LDS_ALL) return pick_lpr<LAY, KT, STEP_LDS_ALL>(lpr);
+    if (mode == STEP_LDS_STATE) return pick_lpr<LAY, KT, STEP_LDS_STATE>(lpr);
+    return pick_lpr<LAY, KT, STEP_GLOBAL>(lpr);
+}
+
+static const void* pick(int lay, int kprec, int mode, int lpr) {
+    if (kprec == SVM_KERNEL_FP64) {
+        if (lay == LAY_DENSE) return pick_mode<LAY_DENSE, double>(mode, lpr);
+        if (lay == LAY_CSR_TABLE) return pick_mode<LAY_CSR_TABLE, double>(mode, lpr);
+        return pick_mode<LAY_CSR_SLOT, double>(mode, lpr);
+    }
+    if (lay == LAY_DENSE) return pick_mode<LAY_DENSE, float>(mode, lpr);
+    if (lay == LAY_CSR_TABLE) return pick_mode<LAY_CSR_TABLE, float>(mode, lpr);
+    return pick_mode<LAY_CSR_SLOT, float>(mode, lpr);
+}
+
+hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, size_t lds, hipStream_t s) {
+    const void* fn = pick(a.lay, kprec, a.mode, lpr);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    StepArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchCooperativeKernel(fn, dim3(G), dim3(STEP_BLOCK), args, (unsigned)lds, s);
+}
+
+int step_max_blocks(int lay, int lpr, int kprec, int mode, size_t lds) {
+    const void* fn = pick(lay, kprec, mode, lpr);
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, STEP_BLOCK, lds) != hipSuccess) return 0;
+    return nb * device_cu_count();
+}
+
+}  // namespace svm

@@ -21,10 +21,12 @@ SVM_EUNSUPPORTED, SVM_ENOMEM, SVM_EBUSY, SVM_EABORT = -6, -7, -8, -9
 SVM_DENSE_ROW_MAJOR, SVM_DENSE_FEATURE_MAJOR, SVM_CSR = 0, 1, 2
 SVM_KERNEL_FP32, SVM_KERNEL_FP64 = 0, 1
 SVM_FLAG_WARM_START, SVM_FLAG_NO_FINAL_RECOMPUTE = 1, 2
+SVM_FLAG_NO_LDS_PAYLOAD, SVM_FLAG_NO_LDS_STATE = 4, 8
 
 EXPORTS = ["svm_train_workspace_size", "svm_train", "svm_decision", "svm_train_batch", "svm_server_create",
            "svm_server_submit", "svm_server_poll", "svm_server_drain", "svm_server_stats", "svm_server_destroy",
-           "svm_strerror", "svm_version", "svm_debug_select", "svm_debug_set_trace"]
+           "svm_strerror", "svm_version", "svm_debug_select", "svm_debug_set_trace", "svm_debug_set_profile",
+           "svm_debug_step_info"]
 
 
 class svm_problem_t(C.Structure):
@@ -84,6 +86,8 @@ def lib():
                                        C.c_int32, P(C.c_double), P(C.c_int32), P(C.c_double), P(C.c_int32),
                                        C.c_void_p]
         L.svm_debug_set_trace.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.svm_debug_set_profile.argtypes = [C.c_void_p]
+        L.svm_debug_step_info.argtypes = [P(C.c_int32), P(C.c_int32), P(C.c_int32)]
         _lib = L
     return _lib
 
@@ -189,6 +193,17 @@ def svm_debug_set_trace(cap, i_up=None, i_low=None, b_up=None, b_low=None) -> in
         return lib().svm_debug_set_trace(0, None, None, None, None)
     return lib().svm_debug_set_trace(int(cap), i_up.data_ptr(), i_low.data_ptr(), b_up.data_ptr(),
                                      b_low.data_ptr())
+
+
+def svm_debug_set_profile(slots) -> int:
+    """slots: uint64/int64 device tensor of 8 entries, or None to switch the timer off."""
+    return lib().svm_debug_set_profile(slots.data_ptr() if slots is not None else None)
+
+
+def svm_debug_step_info():
+    m, g, l = C.c_int32(), C.c_int32(), C.c_int32()
+    lib().svm_debug_step_info(C.byref(m), C.byref(g), C.byref(l))
+    return m.value, g.value, l.value
 
 
 def svm_train_batch(probs, params, alphas, fs=None, stream=None):

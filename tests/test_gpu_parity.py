@@ -185,6 +185,35 @@ def test_fp64_trajectory_and_contract(S, case):
     P("  iterations", ref.iterations, "dual rel %.2e decision %.2e" % (rel, worst))
 
 
+@pytest.mark.parametrize("flags,mode", [(0, 2), (4, 1), (8, 0)], ids=["rows_in_lds", "state_in_lds", "all_in_hbm"])
+@pytest.mark.parametrize("case", [
+    ("cfg1_n2000", lambda: g.config1()),
+    ("cfg2_n3000_earliest_multi", lambda: sub(g.config2(heuristic=g.EARLIEST), 3000)),
+    ("cfg4_n5000_lazy_multi", lambda: sub(g.config4(), 5000)),
+], ids=lambda c: c[0])
+def test_residency_modes_follow_the_same_trajectory(S, case, flags, mode):
+    """Per-row state and rows kept in LDS, state only, or nothing: the same FP64 trajectory."""
+    name, make = case
+    cfg = make()
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP64, trace_cap=100_000, flags=flags, grid_blocks=8)
+    assert out.rc == S.SVM_OK
+    assert S.svm_debug_step_info()[0] == mode
+    ref = O.train_config(cfg, trace_cap=100_000)
+    assert out.result["iterations"] == ref.iterations
+    assert first_divergence(tr, ref.trace) == -1
+    np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
+
+
+@pytest.mark.parametrize("grid", [1, 2, 7, 64, 256])
+def test_grid_size_does_not_change_the_trajectory(S, grid):
+    cfg = sub(g.config2(heuristic=g.EARLIEST), 3000)
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP64, trace_cap=100_000, grid_blocks=grid)
+    assert out.rc == S.SVM_OK
+    ref = O.train_config(cfg, trace_cap=100_000)
+    assert first_divergence(tr, ref.trace) == -1
+    assert out.result["iterations"] == ref.iterations
+
+
 def test_feature_major_layout_is_identical(S):
     import torch
     cfg = g.config1(n=1500, d=9)
