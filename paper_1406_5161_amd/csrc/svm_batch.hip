@@ -1,0 +1,632 @@
+// svm_batch.hip -- many independent training problems in one persistent launch.
+//
+// One workgroup solves one whole problem: the SMO loop of Alg. 2 / Alg. 4, the
+// shrinking driver of Alg. 5 (or its multi-reconstruction variant), gradient
+// reconstruction (Alg. 6), the closing FP64-accumulated recompute of f and the
+// threshold of the paper's Sec. 3.1 all run inside the workgroup, so problems
+// never wait for each other and a problem's result does not depend on what
+// else is resident.  Workgroups take problems by ticket from a descriptor
+// ring; when serving, the host keeps publishing descriptors into pinned
+// memory while the loop runs (continuous batching) and the loop ends once the
+// host asks it to and the ring is drained.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "svm_device.h"
+#include "svm_internal.h"
+
+namespace svm {
+
+constexpr int BB = BATCH_BLOCK;
+constexpr int BNW = BB / 64;
+constexpr int SUMR = 8;                   // rows of A per tile in block-local kernel sums
+constexpr size_t BATCH_LDS = 120 * 1024;  // dynamic LDS of the batched loop
+
+struct BatchShared {
+    BatchDesc P;
+    double v[2 * BNW];
+    int i[2 * BNW];
+    int wc[BNW];
+    double pair[4];
+    double red[BNW][SUMR];
+    double na[SUMR];
+    long long cnt;
+    int ticket;
+    int prev_n;
+};
+
+// Descriptor fields made wave-uniform (scalar registers) after the LDS broadcast.
+template <typename T>
+DEV T* uptr(T* p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffull));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
+DEV int ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
+DEV long long ull_(long long v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffll));
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+DEV double ud(double v) { return __longlong_as_double(ull_(__double_as_longlong(v))); }
+
+DEV BatchDesc uniform_desc(const BatchDesc& S) {
+    BatchDesc P;
+    P.n = ui(S.n); P.d = ui(S.d); P.dpad = ui(S.dpad); P.lay = ui(S.lay);
+    P.x = uptr(S.x); P.row_ptr = uptr(S.row_ptr); P.col = uptr(S.col); P.val = uptr(S.val);
+    P.pattern_only = ui(S.pattern_only); P.lpr = ui(S.lpr);
+    P.y = uptr(S.y);
+    P.C = ud(S.C); P.gamma = ud(S.gamma); P.eps = ud(S.eps);
+    P.shrink_mode = ui(S.shrink_mode); P.kprec = ui(S.kprec);
+    P.H = ull_(S.H); P.max_iter = ull_(S.max_iter);
+    P.flags = (uint32_t)ui((int)S.flags); P.pad = 0;
+    P.alpha = uptr(S.alpha); P.f = uptr(S.f); P.status = uptr(S.status); P.act = uptr(S.act);
+    P.list_w = uptr(S.list_w); P.list_z = uptr(S.list_z); P.coef = uptr(S.coef); P.res = uptr(S.res);
+    return P;
+}
+
+// group sum over `lpr` consecutive lanes (lpr a power of two <= 64)
+template <typename T>
+DEV T group_sum(T v, int lpr) {
+    for (int off = 1; off < lpr; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Stable in-place-compatible block scan of keep flags for one chunk; returns the
+// position of this thread's kept entry relative to `base_out` and the chunk total.
+DEV int block_scan_keep(bool keep, int* s_wc, int& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(keep);
+    const int wpre = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wc[wid] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < BNW; ++w) {
+        const int c = s_wc[w];
+        off += (w < wid) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return off + wpre;
+}
+
+template <typename KT>
+DEV void row_dist(const BatchDesc& P, const float2* pairv, int i, int gl, int lpr, KT nuu, KT nll, KT& du2,
+                  KT& dl2) {
+    if (P.lay == LAY_DENSE) {
+        const float4* x4 = reinterpret_cast<const float4*>(P.x + (size_t)i * P.dpad);
+        const float4* p4 = reinterpret_cast<const float4*>(pairv);
+        KT a = 0, b = 0;
+        for (int k4 = gl; k4 < P.dpad / 4; k4 += lpr) {
+            const float4 v = x4[k4];
+            const float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
+            if constexpr (std::is_same<KT, double>::value) {
+#pragma clang fp contract(off)
+                double t;
+                t = (double)v.x - (double)q0.x; a = a + t * t;
+                t = (double)v.x - (double)q0.y; b = b + t * t;
+                t = (double)v.y - (double)q0.z; a = a + t * t;
+                t = (double)v.y - (double)q0.w; b = b + t * t;
+                t = (double)v.z - (double)q1.x; a = a + t * t;
+                t = (double)v.z - (double)q1.y; b = b + t * t;
+                t = (double)v.w - (double)q1.z; a = a + t * t;
+                t = (double)v.w - (double)q1.w; b = b + t * t;
+            } else {
+                float t;
+                t = v.x - q0.x; a = fmaf(t, t, a);
+                t = v.x - q0.y; b = fmaf(t, t, b);
+                t = v.y - q0.z; a = fmaf(t, t, a);
+                t = v.y - q0.w; b = fmaf(t, t, b);
+                t = v.z - q1.x; a = fmaf(t, t, a);
+                t = v.z - q1.y; b = fmaf(t, t, b);
+                t = v.w - q1.z; a = fmaf(t, t, a);
+                t = v.w - q1.w; b = fmaf(t, t, b);
+            }
+        }
+        du2 = group_sum(a, lpr);
+        dl2 = group_sum(b, lpr);
+    } else {
+        const int p0 = P.row_ptr[i], p1 = P.row_ptr[i + 1];
+        KT nn = 0, su = 0, sl = 0;
+        for (int p = p0 + gl; p < p1; p += lpr) {
+            const int c = P.col[p];
+            const KT v = P.pattern_only ? (KT)1 : (KT)P.val[p];
+            const float2 ul = pairv[c];
+            nn += v * v;
+            su += v * (KT)ul.x;
+            sl += v * (KT)ul.y;
+        }
+        nn = group_sum(nn, lpr);
+        su = group_sum(su, lpr);
+        sl = group_sum(sl, lpr);
+        du2 = nn + nuu - (KT)2 * su;
+        dl2 = nn + nll - (KT)2 * sl;
+        if (du2 < (KT)0) du2 = (KT)0;
+        if (dl2 < (KT)0) dl2 = (KT)0;
+    }
+}
+
+// Selection over the active list from (f, alpha, y) in global memory; every thread gets the result.
+DEV void select_block(const BatchDesc& P, int nact, BatchShared& sh, double& bu, int& iu, double& bl, int& il) {
+    bu = INFINITY; bl = -INFINITY; iu = IDX_NONE; il = IDX_NONE;
+    for (int t = threadIdx.x; t < nact; t += BB) {
+        const int i = P.act[t];
+        const uint8_t st = st_make(P.y[i] > 0, ld_agent(P.alpha + i), P.C);
+        const double fi = P.f[i];
+        if (st_in_up(st) && better_up(fi, i, bu, iu)) { bu = fi; iu = i; }
+        if (st_in_low(st) && better_low(fi, i, bl, il)) { bl = fi; il = i; }
+    }
+    block_reduce_sel_all<BB>(bu, iu, bl, il, sh.v, sh.i);
+    __syncthreads();
+    if (iu == IDX_NONE) iu = -1;
+    if (il == IDX_NONE) il = -1;
+}
+
+// Stable compaction over 0..n-1: list = ids with pred(i) (0: shrunk, i.e. status bit 3 set;
+// 1: alpha > 0, with coefficient alpha * y).  Returns the count (all threads).
+template <int PRED>
+DEV int compact_block(const BatchDesc& P, int n, int32_t* list, double* coef, BatchShared& sh) {
+    int out = 0;
+    for (int base = 0; base < n; base += BB) {
+        const int i = base + threadIdx.x;
+        bool k = false;
+        if (i < n) {
+            if (PRED == 0) k = (P.status[i] & 8) != 0;
+            else k = ld_agent(P.alpha + i) > 0.0;
+        }
+        int tot;
+        const int pos = block_scan_keep(k, sh.wc, tot);
+        if (k) {
+            list[out + pos] = i;
+            if (coef) coef[out + pos] = ld_agent(P.alpha + i) * (P.y[i] > 0 ? 1.0 : -1.0);
+        }
+        out += tot;
+    }
+    __syncthreads();
+    return out;
+}
+
+// f[a] = sum_j coef_j K(x_a, x_{z_j}) - y_a for the rows in `rows` (or 0..na-1), block-local (Alg. 6).
+template <typename KT>
+__device__ __attribute__((noinline)) void kernel_sum_block(const BatchDesc& P, const int32_t* rows, int na, int nz, float* tile, BatchShared& sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const bool dense = P.lay == LAY_DENSE;
+    const int W = dense ? P.dpad : P.d;
+    const KT gam = (KT)P.gamma;
+    for (int r0 = 0; r0 < na; r0 += SUMR) {
+        const int nr = min(SUMR, na - r0);
+        for (int e = tid; e < SUMR * W; e += BB) tile[e] = 0.f;
+        __syncthreads();
+        if (dense) {
+            for (int e = tid; e < nr * W; e += BB) {
+                const int r = e / W, k = e % W;
+                const int a = rows ? rows[r0 + r] : r0 + r;
+                tile[e] = P.x[(size_t)a * P.dpad + k];
+            }
+        } else {
+            for (int r = 0; r < nr; ++r) {
+                const int a = rows ? rows[r0 + r] : r0 + r;
+                for (int p = P.row_ptr[a] + tid; p < P.row_ptr[a + 1]; p += BB)
+                    tile[r * W + P.col[p]] = P.pattern_only ? 1.f : P.val[p];
+            }
+        }
+        __syncthreads();
+        if (!dense) {
+            for (int r = wid; r < nr; r += BNW) {
+                KT s = 0;
+                for (int k = lane; k < W; k += 64) {
+                    const KT v = (KT)tile[r * W + k];
+                    s += v * v;
+                }
+                s = wave_sum(s);
+                if (lane == 0) sh.na[r] = (double)s;
+            }
+            __syncthreads();
+        }
+        double acc[SUMR];
+#pragma unroll
+        for (int r = 0; r < SUMR; ++r) acc[r] = 0.0;
+        for (int jb = tid; jb < nz; jb += BB) {
+            const int j = P.list_z[jb];
+            const double cj = P.coef[jb];
+            KT dist[SUMR];
+#pragma unroll
+            for (int r = 0; r < SUMR; ++r) dist[r] = 0;
+            if (dense) {
+                const float4* xb = reinterpret_cast<const float4*>(P.x + (size_t)j * P.dpad);
+                for (int k4 = 0; k4 < P.dpad / 4; ++k4) {
+                    const float4 v = xb[k4];
+#pragma unroll
+                    for (int r = 0; r < SUMR; ++r) {
+                        if (r < nr) {
+                            const float4 q = reinterpret_cast<const float4*>(tile + r * W)[k4];
+                            if constexpr (std::is_same<KT, double>::value) {
+#pragma clang fp contract(off)
+                                double t, s = dist[r];
+                                t = (double)q.x - (double)v.x; s = s + t * t;
+                                t = (double)q.y - (double)v.y; s = s + t * t;
+                                t = (double)q.z - (double)v.z; s = s + t * t;
+                                t = (double)q.w - (double)v.w; s = s + t * t;
+                                dist[r] = s;
+                            } else {
+                                float t, s = dist[r];
+                                t = q.x - v.x; s = fmaf(t, t, s);
+                                t = q.y - v.y; s = fmaf(t, t, s);
+                                t = q.z - v.z; s = fmaf(t, t, s);
+                                t = q.w - v.w; s = fmaf(t, t, s);
+                                dist[r] = s;
+                            }
+                        }
+                    }
+                }
+            } else {
+                KT nb = 0;
+                for (int p = P.row_ptr[j]; p < P.row_ptr[j + 1]; ++p) {
+                    const int c = P.col[p];
+                    const KT v = P.pattern_only ? (KT)1 : (KT)P.val[p];
+                    nb += v * v;
+#pragma unroll
+                    for (int r = 0; r < SUMR; ++r)
+                        if (r < nr) dist[r] += v * (KT)tile[r * W + c];
+                }
+#pragma unroll
+                for (int r = 0; r < SUMR; ++r) {
+                    KT d2 = (KT)sh.na[r < nr ? r : 0] + nb - (KT)2 * dist[r];
+                    dist[r] = d2 < (KT)0 ? (KT)0 : d2;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < SUMR; ++r)
+                if (r < nr) acc[r] += cj * (double)kexp(-gam * dist[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < SUMR; ++r) {
+            const double v = wave_sum(acc[r]);
+            if (lane == 0) sh.red[wid][r] = v;
+        }
+        __syncthreads();
+        if (tid < nr) {
+            double v = 0.0;
+            for (int w = 0; w < BNW; ++w) v += sh.red[w][tid];
+            const int a = rows ? rows[r0 + tid] : r0 + tid;
+            P.f[a] = v - (P.y[a] > 0 ? 1.0 : -1.0);
+        }
+        __syncthreads();
+    }
+}
+
+// The whole solve of one problem by the calling workgroup.
+template <typename KT>
+DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
+    const BatchDesc& P = sh.P;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n = P.n;
+    const int lpr = P.lpr;
+    const int NG = BB / lpr, g = tid / lpr, gl = tid % lpr;
+    const double C = P.C;
+    const bool dense = P.lay == LAY_DENSE;
+    float2* pairv = reinterpret_cast<float2*>(dyn);
+    const int pair_entries = dense ? P.dpad : P.d;
+    int* prev_cols = reinterpret_cast<int*>(dyn + sizeof(float2) * (size_t)pair_entries);
+    const size_t tile_off = (sizeof(float2) * (size_t)pair_entries + sizeof(int) * 2 * 4096 + 15) & ~(size_t)15;
+    float* tile = reinterpret_cast<float*>(dyn + tile_off);
+    const unsigned long long t_start = wall_clock64();
+
+    // initial state: alpha = 0, f = -y, everything active (status bit 3 = shrunk)
+    for (int i = tid; i < n; i += BB) {
+        const bool yp = P.y[i] > 0;
+        st_agent(P.alpha + i, 0.0);
+        P.f[i] = yp ? -1.0 : 1.0;
+        P.status[i] = st_make(yp, 0.0, C);
+        P.act[i] = i;
+    }
+    if (!dense)
+        for (int k = tid; k < P.d; k += BB) pairv[k] = make_float2(0.f, 0.f);
+    if (tid == 0) sh.prev_n = 0;
+    __syncthreads();
+
+    int nact = n;
+    double bu, bl;
+    int iu, il;
+    select_block(P, nact, sh, bu, iu, bl, il);
+    bool shrinking = P.shrink_mode != SVM_SHRINK_NONE;
+    double thr = shrinking ? 20.0 * P.eps : 2.0 * P.eps;
+    const long long H = shrinking ? P.H : 0;
+    long long counter = H, iter = 0, passes = 0, shrunk = 0;
+    int n_recon = 0, rechecks = 0, status = SVM_OK;
+    const bool final_recompute = P.kprec == SVM_KERNEL_FP32 && !(P.flags & SVM_FLAG_NO_FINAL_RECOMPUTE);
+
+    for (;;) {
+        // ---- SMO iterations of this phase
+        while (bl - bu > thr) {
+            if (iter >= P.max_iter) { status = SVM_NOT_CONVERGED; break; }
+            const double au = ld_agent(P.alpha + iu), al = ld_agent(P.alpha + il);
+            const int yu = P.y[iu] > 0 ? 1 : -1, yl = P.y[il] > 0 ? 1 : -1;
+            if (dense) {
+                const float* xu = P.x + (size_t)iu * P.dpad;
+                const float* xl = P.x + (size_t)il * P.dpad;
+                for (int k = tid; k < P.dpad; k += BB) pairv[k] = make_float2(xu[k], xl[k]);
+                __syncthreads();
+                if (tid == 0) {
+                    double s;
+                    if constexpr (std::is_same<KT, double>::value) {
+#pragma clang fp contract(off)
+                        double a = 0.0;
+                        for (int k = 0; k < P.dpad; ++k) {
+                            const double t = (double)pairv[k].x - (double)pairv[k].y;
+                            a = a + t * t;
+                        }
+                        s = exp(-P.gamma * a);
+                    } else {
+                        float a = 0.f;
+                        for (int k = 0; k < P.dpad; ++k) {
+                            const float t = pairv[k].x - pairv[k].y;
+                            a = fmaf(t, t, a);
+                        }
+                        s = (double)expf(-(float)P.gamma * a);
+                    }
+                    sh.pair[0] = s;
+                }
+            } else {
+                const int pu0 = P.row_ptr[iu], pu1 = P.row_ptr[iu + 1];
+                const int pl0 = P.row_ptr[il], pl1 = P.row_ptr[il + 1];
+                const int nu = pu1 - pu0, nl = pl1 - pl0;
+                for (int j = tid; j < sh.prev_n; j += BB) pairv[prev_cols[j]] = make_float2(0.f, 0.f);
+                __syncthreads();
+                float* pf = reinterpret_cast<float*>(pairv);
+                for (int p = tid; p < nu; p += BB) {
+                    const int c = P.col[pu0 + p];
+                    pf[2 * c] = P.pattern_only ? 1.f : P.val[pu0 + p];
+                    prev_cols[p] = c;
+                }
+                for (int p = tid; p < nl; p += BB) {
+                    const int c = P.col[pl0 + p];
+                    pf[2 * c + 1] = P.pattern_only ? 1.f : P.val[pl0 + p];
+                    prev_cols[nu + p] = c;
+                }
+                __syncthreads();
+                if (wid == 0) {
+                    KT su = 0, sl = 0, dot = 0;
+                    for (int p = lane; p < nu; p += 64) {
+                        const KT v = P.pattern_only ? (KT)1 : (KT)P.val[pu0 + p];
+                        su += v * v;
+                    }
+                    for (int p = lane; p < nl; p += 64) {
+                        const KT v = P.pattern_only ? (KT)1 : (KT)P.val[pl0 + p];
+                        sl += v * v;
+                        dot += v * (KT)pairv[P.col[pl0 + p]].x;
+                    }
+                    su = wave_sum(su);
+                    sl = wave_sum(sl);
+                    dot = wave_sum(dot);
+                    if (lane == 0) {
+                        KT d2 = su + sl - (KT)2 * dot;
+                        if (d2 < (KT)0) d2 = (KT)0;
+                        sh.pair[0] = (double)kexp((KT)(-(KT)P.gamma * d2));
+                        sh.pair[1] = (double)su;
+                        sh.pair[2] = (double)sl;
+                        sh.prev_n = nu + nl;
+                    }
+                }
+            }
+            __syncthreads();
+            const PairNew pn = pair_update(au, al, yu, yl, bu, bl, sh.pair[0], C);
+            const KT gam = (KT)P.gamma;
+            const KT nuu = dense ? (KT)0 : (KT)sh.pair[1], nll = dense ? (KT)0 : (KT)sh.pair[2];
+            bool do_shrink = false;
+            if (H > 0) {
+                --counter;
+                do_shrink = counter == 0;
+            }
+            double cbu = INFINITY, cbl = -INFINITY;
+            int ciu = IDX_NONE, cil = IDX_NONE;
+            int newcount = 0;
+            for (int base = 0; base < nact; base += NG) {
+                const int t = base + g;
+                const bool valid = t < nact;
+                const int i = valid ? P.act[t] : 0;
+                bool keep = false;
+                if (valid) {
+                    KT du2, dl2;
+                    row_dist<KT>(P, pairv, i, gl, lpr, nuu, nll, du2, dl2);
+                    if (gl == 0) {
+                        const double ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2);
+                        const double kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2);
+                        double fi;
+                        {
+#pragma clang fp contract(off)
+                            fi = P.f[i] + (pn.cu * ku + pn.cl * kl);
+                        }
+                        P.f[i] = fi;
+                        uint8_t st = P.status[i];
+                        if (i == iu) {
+                            st = st_make(yu > 0, pn.au, C);
+                            P.status[i] = st;
+                            st_agent(P.alpha + i, pn.au);
+                        } else if (i == il) {
+                            st = st_make(yl > 0, pn.al, C);
+                            P.status[i] = st;
+                            st_agent(P.alpha + i, pn.al);
+                        }
+                        keep = !(do_shrink && shrink_rule(st, fi, bu, bl));
+                        if (!keep) P.status[i] = st | 8;
+                        if (keep) {
+                            if (st_in_up(st) && better_up(fi, i, cbu, ciu)) { cbu = fi; ciu = i; }
+                            if (st_in_low(st) && better_low(fi, i, cbl, cil)) { cbl = fi; cil = i; }
+                        }
+                    }
+                }
+                if (do_shrink) {
+                    int tot;
+                    const int pos = block_scan_keep(keep, sh.wc, tot);
+                    if (keep) P.act[newcount + pos] = i;
+                    newcount += tot;
+                }
+            }
+            block_reduce_sel_all<BB>(cbu, ciu, cbl, cil, sh.v, sh.i);
+            __syncthreads();
+            bu = cbu; bl = cbl;
+            iu = ciu == IDX_NONE ? -1 : ciu;
+            il = cil == IDX_NONE ? -1 : cil;
+            if (do_shrink) {
+                shrunk += nact - newcount;
+                nact = newcount;
+                ++passes;
+                counter = nact < H ? nact : H;
+                if (counter < 1) counter = 1;
+            }
+            ++iter;
+        }
+        if (status != SVM_OK) break;
+        if (shrinking) {
+            // the active set meets the tolerance: rebuild f of the shrunk samples (Alg. 6)
+            const int nw = compact_block<0>(P, n, P.list_w, nullptr, sh);
+            const int nz = compact_block<1>(P, n, P.list_z, P.coef, sh);
+            if (nw > 0) kernel_sum_block<KT>(P, P.list_w, nw, nz, tile, sh);
+            for (int i = tid; i < n; i += BB) {
+                P.status[i] &= 7;
+                P.act[i] = i;
+            }
+            __syncthreads();
+            nact = n;
+            ++n_recon;
+            select_block(P, nact, sh, bu, iu, bl, il);
+            if (bl - bu > 2.0 * P.eps) {
+                thr = 2.0 * P.eps;
+                if (P.shrink_mode == SVM_SHRINK_SINGLE) shrinking = false;
+                counter = H;
+                continue;
+            }
+        }
+        if (final_recompute && rechecks < 2) {
+            ++rechecks;
+            const int nz = compact_block<1>(P, n, P.list_z, P.coef, sh);
+            kernel_sum_block<KT>(P, nullptr, n, nz, tile, sh);
+            select_block(P, nact, sh, bu, iu, bl, il);
+            if (bl - bu > 2.0 * P.eps) {
+                thr = 2.0 * P.eps;
+                counter = H;
+                continue;
+            }
+        }
+        break;
+    }
+    if (status == SVM_NOT_CONVERGED && nact < n) {
+        const int nw = compact_block<0>(P, n, P.list_w, nullptr, sh);
+        const int nz = compact_block<1>(P, n, P.list_z, P.coef, sh);
+        if (nw > 0) kernel_sum_block<KT>(P, P.list_w, nw, nz, tile, sh);
+        for (int i = tid; i < n; i += BB) {
+            P.status[i] &= 7;
+            P.act[i] = i;
+        }
+        __syncthreads();
+        nact = n;
+        ++n_recon;
+        select_block(P, nact, sh, bu, iu, bl, il);
+    }
+    // ---- threshold and summary
+    double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0;
+    for (int i = tid; i < n; i += BB) {
+        const double a = ld_agent(P.alpha + i);
+        const double yi = P.y[i] > 0 ? 1.0 : -1.0;
+        if (a > 0.0 && a < C) { v0 += P.f[i]; v1 += 1.0; }
+        v2 += a;
+        v3 += a * yi * (P.f[i] + yi);
+        if (a > 0.0) v4 += 1.0;
+        if (a >= C) v5 += 1.0;
+    }
+    v0 = wave_sum(v0); v1 = wave_sum(v1); v2 = wave_sum(v2);
+    v3 = wave_sum(v3); v4 = wave_sum(v4); v5 = wave_sum(v5);
+    if (lane == 0) {
+        sh.red[wid][0] = v0; sh.red[wid][1] = v1; sh.red[wid][2] = v2;
+        sh.red[wid][3] = v3; sh.red[wid][4] = v4; sh.red[wid][5] = v5;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double s[6] = {0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < BNW; ++w)
+            for (int k = 0; k < 6; ++k) s[k] += sh.red[w][k];
+        BatchResult* R = P.res;
+        const double beta = s[1] > 0 ? s[0] / s[1] : 0.5 * (bu + bl);
+        __hip_atomic_store(&R->beta, beta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->b_up, bu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->b_low, bl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->dual_obj, s[2] - 0.5 * s[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->iterations, iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->n_sv, (int32_t)s[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->n_bsv, (int32_t)s[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->n_recon, n_recon, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->status, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->shrink_passes, passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->shrunk_total, shrunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->t_start, t_start, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->t_end, wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();
+}
+
+template <typename KT>
+__global__ __launch_bounds__(BB) void smo_batch_kernel(BatchArgs A) {
+    extern __shared__ __align__(16) unsigned char dyn[];
+    __shared__ BatchShared sh;
+    const int tid = threadIdx.x;
+    for (;;) {
+        // ---- take a ticket; wait until its descriptor is published or the host stops the loop
+        if (tid == 0) {
+            const int t = atomicAdd(A.head, 1);
+            int ok = 0;
+            if (A.fixed_tail > 0) {
+                ok = t < A.fixed_tail;
+            } else {
+                const unsigned long long t0 = wall_clock64();
+                for (;;) {
+                    const int tail = __hip_atomic_load(A.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    if (t < tail) { ok = 1; break; }
+                    if (__hip_atomic_load(A.shutdown, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                        // published before the stop request?
+                        ok = t < __hip_atomic_load(A.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                        break;
+                    }
+                    if (wall_clock64() - t0 > A.idle_limit) break;
+                    __builtin_amdgcn_s_sleep(127);
+                }
+            }
+            sh.ticket = ok ? t : -1;
+            if (ok) sh.P = A.descs[t & (A.capacity - 1)];
+        }
+        __syncthreads();
+        if (sh.ticket < 0) break;
+        solve_one<KT>(sh, dyn);
+    }
+}
+
+hipError_t launch_batch(const BatchArgs& a, int workgroups, int kprec, hipStream_t s) {
+    BatchArgs c = a;
+    if (kprec == SVM_KERNEL_FP64) {
+        (void)hipFuncSetAttribute((const void*)smo_batch_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)BATCH_LDS);
+        smo_batch_kernel<double><<<workgroups, BB, BATCH_LDS, s>>>(c);
+    } else {
+        (void)hipFuncSetAttribute((const void*)smo_batch_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)BATCH_LDS);
+        smo_batch_kernel<float><<<workgroups, BB, BATCH_LDS, s>>>(c);
+    }
+    return hipGetLastError();
+}
+
+int batch_max_workgroups(int kprec) {
+    const void* fn = kprec == SVM_KERNEL_FP64 ? (const void*)smo_batch_kernel<double>
+                                              : (const void*)smo_batch_kernel<float>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BATCH_LDS);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, BB, BATCH_LDS) != hipSuccess) return 0;
+    return nb * device_cu_count();
+}
+
+}  // namespace svm

@@ -168,3 +168,59 @@ hipError_t launch_check_pattern(int nnz, const float* val, int32_t* flag, hipStr
 int device_cu_count();
 
 }  // namespace svm
+
+namespace svm {
+
+// ---- batched / serving solver: one workgroup solves one whole problem
+
+constexpr int BATCH_BLOCK = 512;
+
+struct BatchResult {
+    double beta, b_up, b_low, dual_obj;
+    long long iterations;
+    int32_t n_sv, n_bsv, n_recon, status;
+    long long shrink_passes, shrunk_total;
+    unsigned long long t_start, t_end;   // device wall clock (100 MHz) around the solve
+    int32_t done;                        // set last (release) when the fields above are final
+    int32_t pad;
+};
+
+struct BatchDesc {
+    int32_t n, d, dpad, lay;             // lay: LAY_DENSE or LAY_CSR_TABLE
+    const float* x;                      // dense, packed [n][dpad]
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const float* val;
+    int32_t pattern_only, lpr;           // lpr: lanes per row (dense and CSR)
+    const int8_t* y;
+    double C, gamma, eps;
+    int32_t shrink_mode, kprec;
+    long long H, max_iter;
+    uint32_t flags;
+    int32_t pad;
+    // per-problem device workspace
+    double* alpha;
+    double* f;
+    uint8_t* status;
+    int32_t* act;
+    int32_t* list_w;
+    int32_t* list_z;
+    double* coef;
+    BatchResult* res;                    // device or pinned host memory
+};
+
+struct BatchArgs {
+    const BatchDesc* descs;              // descriptor ring (device or pinned host)
+    int32_t capacity;                    // ring size (power of two)
+    int32_t* head;                       // device counter: next ticket
+    const int32_t* tail;                 // number of published descriptors (host-written when serving)
+    const int32_t* shutdown;             // host sets 1 to stop the loop once the queue is drained
+    unsigned long long idle_limit;       // watchdog: wall-clock ticks a workgroup may wait for work
+    int32_t fixed_tail;                  // > 0: a fixed batch (tail is this value, no polling)
+    int32_t pad;
+};
+
+hipError_t launch_batch(const BatchArgs& a, int workgroups, int kprec, hipStream_t s);
+int batch_max_workgroups(int kprec);
+
+}  // namespace svm

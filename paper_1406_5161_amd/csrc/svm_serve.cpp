@@ -1,17 +1,521 @@
-// svm_serve.cpp -- batched training and the serving loop (continuous batching).
+// svm_serve.cpp -- batched training (svm_train_batch) and the serving loop
+// (svm_server_*): continuous batching of SVM training problems on one GPU.
+//
+// Both run the persistent batched kernel of svm_batch.hip, in which one
+// workgroup solves one whole problem.  The batch entry point hands it a fixed
+// list; the server keeps the kernel running and publishes problems into a
+// descriptor ring in pinned host memory as they are admitted.  Admission
+// needs a free slot (at most max_slots problems in flight) and room for the
+// problem's solver state in the server's device-memory arena; otherwise the
+// problem waits in a FIFO and is admitted when a running one completes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "svm_internal.h"
+
+using namespace svm;
+
+namespace {
+
+constexpr size_t SALIGN = 256;
+size_t al(size_t v) { return (v + SALIGN - 1) & ~(SALIGN - 1); }
+int dpad4(int d) { return (d + 3) & ~3; }
+
+// ---- shape autotuning: lanes per row of the batched loop.
+// Rules measured on gfx950 for one workgroup per problem: enough lanes that a
+// row is read with a few 16-byte loads per lane (dense) or about 8 nonzeros per
+// lane (CSR); FP64 dense keeps one lane per row so the distance is summed in
+// feature order.
+int tune_lanes_per_row(const svm_problem_t* p, double avg_nnz, int kprec, int requested) {
+    if (requested) return requested;
+    int l = 1;
+    if (p->layout == SVM_CSR) {
+        while (l < 16 && 8.0 * 2 * l <= avg_nnz) l *= 2;
+    } else {
+        if (kprec == SVM_KERNEL_FP64) return 1;
+        const int f4 = dpad4(p->d) / 4;
+        while (l < 16 && 8 * 2 * l <= f4) l *= 2;
+    }
+    return l;
+}
+
+struct ProbBytes {
+    size_t x, f, status, act, lw, lz, coef, total;
+};
+
+ProbBytes prob_bytes(const svm_problem_t* p, bool need_f) {
+    ProbBytes b{};
+    const size_t n = (size_t)p->n;
+    size_t o = 0;
+    auto take = [&](size_t v) { size_t a = o; o = al(o + v); return a; };
+    b.x = take(p->layout == SVM_CSR ? 0 : sizeof(float) * n * dpad4(p->d));
+    b.f = take(need_f ? sizeof(double) * n : 0);
+    b.status = take(n);
+    b.act = take(sizeof(int32_t) * n);
+    b.lw = take(sizeof(int32_t) * n);
+    b.lz = take(sizeof(int32_t) * n);
+    b.coef = take(sizeof(double) * n);
+    b.total = o;
+    return b;
+}
+
+int check_batch_problem(const svm_problem_t* p, const svm_params_t* q) {
+    if (!p || !q || p->n < 2 || p->d < 1 || !p->y) return SVM_EINVAL;
+    if (!(q->C > 0) || !(q->gamma > 0) || !(q->eps > 0) || q->max_iter <= 0) return SVM_EINVAL;
+    if (q->shrink_mode < 0 || q->shrink_mode > 2) return SVM_EINVAL;
+    if (q->shrink_mode != SVM_SHRINK_NONE && !(q->shrink_param > 0)) return SVM_EINVAL;
+    if (q->kernel_precision != SVM_KERNEL_FP32 && q->kernel_precision != SVM_KERNEL_FP64) return SVM_EINVAL;
+    int l = q->lanes_per_row;
+    if (l < 0 || l > 64 || (l & (l - 1))) return SVM_EINVAL;
+    if (p->layout == SVM_CSR) {
+        if (!p->row_ptr || !p->col || !p->val) return SVM_EINVAL;
+        // LDS of the batched loop: pair table (d) + tile of 16 densified rows (16 d)
+        if (8.0 * p->d + 32768.0 + 64.0 * p->d > 118.0 * 1024) return SVM_EUNSUPPORTED;
+    } else {
+        if (!p->x) return SVM_EINVAL;
+        if (p->layout == SVM_DENSE_ROW_MAJOR && p->ldx < p->d) return SVM_EINVAL;
+        if (p->layout == SVM_DENSE_FEATURE_MAJOR && p->ldx < p->n) return SVM_EINVAL;
+        if (8.0 * dpad4(p->d) + 32768.0 + 64.0 * dpad4(p->d) > 118.0 * 1024) return SVM_EUNSUPPORTED;
+    }
+    return SVM_OK;
+}
+
+int64_t shrink_h(const svm_params_t* q, int n) {
+    if (q->shrink_mode == SVM_SHRINK_NONE) return 0;
+    double h = q->shrink_kind == SVM_KIND_FIXED ? q->shrink_param : std::ceil(q->shrink_param * (double)n);
+    return (int64_t)std::max(1.0, h);
+}
+
+// Validate on the device and fill a descriptor; `ws` holds prob_bytes(p) bytes.
+int prepare(const svm_problem_t* p, const svm_params_t* q, double* alpha, double* f_user, unsigned char* ws,
+            BatchResult* res, Ctl* vctl, hipStream_t s, BatchDesc* D) {
+    hipError_t e = hipMemsetAsync(vctl, 0, sizeof(Ctl), s);
+    if (e == hipSuccess)
+        e = launch_validate(p->n, p->d, p->layout, p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR, p->row_ptr,
+                            p->col, p->val, p->y, vctl, s);
+    Ctl h{};
+    int32_t nnz = 0, notpat = 1;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, vctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && p->layout == SVM_CSR)
+        e = hipMemcpyAsync(&nnz, p->row_ptr + p->n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return SVM_EHIP;
+    if (h.err & 1) return SVM_EINVAL;
+    if (h.err & 2) return SVM_ENONFINITE;
+    if (h.n_pos == 0 || h.n_neg == 0) return SVM_EONECLASS;
+    if (p->layout == SVM_CSR && h.max_row_nnz > 4096) return SVM_EUNSUPPORTED;
+    const ProbBytes b = prob_bytes(p, f_user == nullptr);
+    memset(D, 0, sizeof(*D));
+    D->n = p->n;
+    D->d = p->d;
+    D->dpad = dpad4(p->d);
+    D->y = p->y;
+    if (p->layout == SVM_CSR) {
+        D->lay = LAY_CSR_TABLE;
+        D->row_ptr = p->row_ptr;
+        D->col = p->col;
+        D->val = p->val;
+        int32_t* flag = reinterpret_cast<int32_t*>(vctl) + 40;
+        e = launch_check_pattern(nnz, p->val, flag, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&notpat, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return SVM_EHIP;
+        D->pattern_only = notpat == 0;
+    } else {
+        D->lay = LAY_DENSE;
+        float* xp = reinterpret_cast<float*>(ws + b.x);
+        e = launch_pack_dense(p->n, p->d, D->dpad, p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR, xp, s);
+        if (e != hipSuccess) return SVM_EHIP;
+        D->x = xp;
+    }
+    const double avg = p->layout == SVM_CSR ? (double)nnz / (double)p->n : 0.0;
+    D->lpr = tune_lanes_per_row(p, avg, q->kernel_precision, q->lanes_per_row);
+    D->C = q->C;
+    D->gamma = q->gamma;
+    D->eps = q->eps;
+    D->shrink_mode = q->shrink_mode;
+    D->kprec = q->kernel_precision;
+    D->H = shrink_h(q, p->n);
+    D->max_iter = q->max_iter;
+    D->flags = q->flags;
+    D->alpha = alpha;
+    D->f = f_user ? f_user : reinterpret_cast<double*>(ws + b.f);
+    D->status = ws + b.status;
+    D->act = reinterpret_cast<int32_t*>(ws + b.act);
+    D->list_w = reinterpret_cast<int32_t*>(ws + b.lw);
+    D->list_z = reinterpret_cast<int32_t*>(ws + b.lz);
+    D->coef = reinterpret_cast<double*>(ws + b.coef);
+    D->res = res;
+    return SVM_OK;
+}
+
+void fill_result(const BatchResult& r, svm_result_t* out) {
+    memset(out, 0, sizeof(*out));
+    out->beta = r.beta;
+    out->b_up = r.b_up;
+    out->b_low = r.b_low;
+    out->dual_obj = r.dual_obj;
+    out->iterations = r.iterations;
+    out->n_sv = r.n_sv;
+    out->n_bsv = r.n_bsv;
+    out->n_recon = r.n_recon;
+    out->status = r.status;
+    out->shrink_passes = r.shrink_passes;
+    out->shrunk_total = r.shrunk_total;
+    out->n_launches = 1;
+    out->grid_blocks = 1;
+    out->ms_step = (double)(r.t_end - r.t_start) * 1e-5;   // 100 MHz device wall clock
+    out->ms_total = out->ms_step;
+}
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ server
+
+struct Arena {
+    // first-fit free list over [0, size)
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> bytes
+    void init(size_t s) { size = s; free_.clear(); if (s) free_[0] = s; }
+    bool alloc(size_t bytes, size_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t noff = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[noff] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+constexpr int RING = 4096;
+
+struct Pending {
+    int64_t ticket;
+    svm_problem_t prob;
+    svm_params_t params;
+    double* alpha;
+};
+
+struct Server {
+    size_t budget = 0;
+    int max_slots = 0;
+    int workgroups = 0;
+    hipStream_t ks = nullptr, cs = nullptr;
+    unsigned char* arena_mem = nullptr;
+    Arena arena;
+    BatchDesc* ring = nullptr;        // pinned
+    BatchResult* results = nullptr;   // pinned
+    int32_t* tail = nullptr;          // pinned
+    int32_t* shutdown = nullptr;      // pinned
+    int32_t* head = nullptr;          // device
+    Ctl* vctl = nullptr;              // device scratch for validation
+    int32_t published = 0;
+    bool kernel_live = false;
+    std::mutex mu;
+    struct Live {
+        int32_t slot;
+        size_t off, bytes;
+    };
+    std::map<int64_t, Live> live;     // ticket -> resources (published, not yet observed done)
+    std::map<int64_t, svm_result_t> done;
+    std::map<int64_t, int> failed;    // ticket -> error code (rejected at admission)
+    std::deque<Pending> waiting;
+    std::map<int64_t, int32_t> ticket_slot;
+    int64_t next_ticket = 0;
+    int64_t n_admitted = 0, n_deferred = 0, n_completed = 0;
+
+    // move problems whose done flag is set out of `live`
+    void scan_done() {
+        for (auto it = live.begin(); it != live.end();) {
+            BatchResult& r = results[it->second.slot];
+            if (__atomic_load_n(&r.done, __ATOMIC_ACQUIRE)) {
+                svm_result_t out;
+                fill_result(r, &out);
+                done[it->first] = out;
+                arena.release(it->second.off, it->second.bytes);
+                ++n_completed;
+                it = live.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+
+    // The loop ends by itself after 2 s without work.  If it has ended, every ticket it claimed is
+    // done, and the published tickets still live were never claimed: they are the last |live|
+    // ones, so a new launch starts its tickets there.
+    void ensure_running() {
+        if (kernel_live && hipStreamQuery(ks) == hipSuccess) kernel_live = false;
+        if (kernel_live) return;
+        scan_done();
+        const int32_t first = published - (int32_t)live.size();
+        if (hipMemcpyAsync(head, &first, sizeof(int32_t), hipMemcpyHostToDevice, ks) != hipSuccess) return;
+        BatchArgs a{};
+        a.descs = ring;
+        a.capacity = RING;
+        a.head = head;
+        a.tail = tail;
+        a.shutdown = shutdown;
+        a.idle_limit = 200ull * 1000 * 1000;
+        a.fixed_tail = 0;
+        if (launch_batch(a, workgroups, SVM_KERNEL_FP32, ks) == hipSuccess) kernel_live = true;
+    }
+
+    // publish one admitted problem; returns an error code for rejected problems
+    int publish(int64_t ticket, const svm_problem_t* p, const svm_params_t* q, double* alpha, size_t off,
+                size_t bytes) {
+        const int32_t slot = published & (RING - 1);
+        BatchDesc D;
+        memset(&results[slot], 0, sizeof(BatchResult));
+        int rc = prepare(p, q, alpha, nullptr, arena_mem + off, &results[slot], vctl, cs, &D);
+        if (rc) return rc;
+        if (hipStreamSynchronize(cs) != hipSuccess) return SVM_EHIP;   // packing done before publishing
+        ring[slot] = D;
+        std::atomic_thread_fence(std::memory_order_release);
+        ++published;
+        __atomic_store_n(tail, published, __ATOMIC_RELEASE);
+        live[ticket] = Live{slot, off, bytes};
+        ticket_slot[ticket] = slot;
+        ++n_admitted;
+        ensure_running();
+        return SVM_OK;
+    }
+
+    bool try_admit(const Pending& w) {
+        const size_t bytes = prob_bytes(&w.prob, true).total;
+        if ((int)live.size() >= max_slots) return false;
+        size_t off = 0;
+        if (!arena.alloc(bytes, &off)) return false;
+        const int rc = publish(w.ticket, &w.prob, &w.params, w.alpha, off, bytes);
+        if (rc) {
+            arena.release(off, bytes);
+            failed[w.ticket] = rc;
+        }
+        return true;
+    }
+
+    void harvest() {
+        scan_done();
+        while (!waiting.empty() && try_admit(waiting.front())) waiting.pop_front();
+        if (!live.empty()) ensure_running();
+    }
+};
+
+}  // namespace
 
 extern "C" {
 
-int svm_train_batch(int32_t, const svm_problem_t*, const svm_params_t*, double* const*, double* const*,
-                    svm_result_t*, void*) {
-    return SVM_EUNSUPPORTED;
+int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* params, double* const* alpha,
+                    double* const* f, svm_result_t* out, void* stream) {
+    if (k < 0 || (k > 0 && (!probs || !params || !alpha || !out))) return SVM_EINVAL;
+    if (k == 0) return SVM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int kprec = params[0].kernel_precision;
+    for (int p = 0; p < k; ++p) {
+        int rc = check_batch_problem(&probs[p], &params[p]);
+        if (rc) return rc;
+        if (!alpha[p] || params[p].kernel_precision != kprec) return SVM_EINVAL;
+    }
+    // one buffer for every problem's solver state, descriptors and results
+    std::vector<size_t> off(k);
+    size_t o = al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) + al(sizeof(Ctl) + 256) + al(64);
+    for (int p = 0; p < k; ++p) {
+        off[p] = o;
+        o += prob_bytes(&probs[p], !(f && f[p])).total;
+    }
+    unsigned char* buf = nullptr;
+    if (hipMalloc(&buf, o) != hipSuccess) return SVM_ENOMEM;
+    BatchDesc* ddesc = reinterpret_cast<BatchDesc*>(buf);
+    BatchResult* dres = reinterpret_cast<BatchResult*>(buf + al(sizeof(BatchDesc) * k));
+    Ctl* vctl = reinterpret_cast<Ctl*>(buf + al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k));
+    int32_t* head = reinterpret_cast<int32_t*>(buf + al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) +
+                                               al(sizeof(Ctl) + 256));
+    std::vector<BatchDesc> hd(k);
+    int rc = SVM_OK;
+    for (int p = 0; p < k && rc == SVM_OK; ++p)
+        rc = prepare(&probs[p], &params[p], alpha[p], f ? f[p] : nullptr, buf + off[p], dres + p, vctl, s, &hd[p]);
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(buf);
+        return rc;
+    }
+    // largest problems first (longest-processing-time order) so the tail of the launch is short
+    std::vector<int> order(k);
+    for (int p = 0; p < k; ++p) order[p] = p;
+    auto cost = [&](int p) {
+        const double row = hd[p].lay == LAY_DENSE ? 4.0 * hd[p].dpad : 40.0;
+        return (double)hd[p].n * (double)hd[p].n * row;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<BatchDesc> sorted(k);
+    for (int t = 0; t < k; ++t) sorted[t] = hd[order[t]];
+    // a fixed batch: tickets run 0..k-1, so a mask wider than any ticket indexes the array directly
+    const int cap = 1 << 30;
+    BatchDesc* dring = ddesc;
+    hipError_t e = hipMemcpyAsync(dring, sorted.data(), sizeof(BatchDesc) * k, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(dres, 0, sizeof(BatchResult) * k, s);
+    if (e == hipSuccess) e = hipMemsetAsync(head, 0, sizeof(int32_t), s);
+    BatchArgs a{};
+    a.descs = dring;
+    a.capacity = cap;
+    a.head = head;
+    a.tail = head;
+    a.shutdown = head;
+    a.idle_limit = 1;
+    a.fixed_tail = k;
+    const int wg = std::max(1, std::min(k, batch_max_workgroups(kprec)));
+    if (e == hipSuccess) e = launch_batch(a, wg, kprec, s);
+    std::vector<BatchResult> hr(k);
+    if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), dres, sizeof(BatchResult) * k, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return SVM_EHIP;
+    int worst = SVM_OK;
+    for (int p = 0; p < k; ++p) {
+        fill_result(hr[p], &out[p]);
+        if (hr[p].status != SVM_OK) worst = hr[p].status;
+    }
+    return worst;
 }
-int svm_server_create(size_t, int32_t, void**) { return SVM_EUNSUPPORTED; }
-int svm_server_submit(void*, const svm_problem_t*, const svm_params_t*, double*, int64_t*) { return SVM_EUNSUPPORTED; }
-int svm_server_poll(void*, int64_t, svm_result_t*) { return SVM_EUNSUPPORTED; }
-int svm_server_drain(void*) { return SVM_EUNSUPPORTED; }
-int svm_server_stats(void*, int64_t*, int64_t*, int64_t*, int64_t*) { return SVM_EUNSUPPORTED; }
-int svm_server_destroy(void*) { return SVM_EUNSUPPORTED; }
+
+int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server) {
+    if (!server || max_slots < 1 || max_slots > RING / 2 || hbm_budget < 4096) return SVM_EINVAL;
+    Server* S = new Server();
+    S->budget = hbm_budget;
+    S->max_slots = max_slots;
+    S->workgroups = std::max(1, std::min(max_slots, batch_max_workgroups(SVM_KERNEL_FP32)));
+    bool ok = hipStreamCreateWithFlags(&S->ks, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc(&S->arena_mem, hbm_budget) == hipSuccess &&
+              hipHostMalloc((void**)&S->ring, sizeof(BatchDesc) * RING, hipHostMallocCoherent) == hipSuccess &&
+              hipHostMalloc((void**)&S->results, sizeof(BatchResult) * RING, hipHostMallocCoherent) == hipSuccess &&
+              hipHostMalloc((void**)&S->tail, 64, hipHostMallocCoherent) == hipSuccess &&
+              hipHostMalloc((void**)&S->shutdown, 64, hipHostMallocCoherent) == hipSuccess &&
+              hipMalloc(&S->head, 64) == hipSuccess && hipMalloc(&S->vctl, sizeof(Ctl) + 256) == hipSuccess;
+    if (!ok) {
+        svm_server_destroy(S);
+        return SVM_ENOMEM;
+    }
+    S->arena.init(hbm_budget);
+    *S->tail = 0;
+    *S->shutdown = 0;
+    memset(S->results, 0, sizeof(BatchResult) * RING);
+    S->ensure_running();
+    if (!S->kernel_live) {
+        svm_server_destroy(S);
+        return SVM_EHIP;
+    }
+    *server = S;
+    return SVM_OK;
+}
+
+int svm_server_submit(void* server, const svm_problem_t* prob, const svm_params_t* params, double* alpha,
+                      int64_t* ticket) {
+    Server* S = (Server*)server;
+    if (!S || !ticket || !alpha) return SVM_EINVAL;
+    int rc = check_batch_problem(prob, params);
+    if (rc) return rc;
+    if (params->kernel_precision != SVM_KERNEL_FP32) return SVM_EINVAL;
+    if (prob_bytes(prob, true).total > S->budget) return SVM_ENOMEM;
+    std::lock_guard<std::mutex> lk(S->mu);
+    Pending w{S->next_ticket++, *prob, *params, alpha};
+    *ticket = w.ticket;
+    S->harvest();
+    if (!S->waiting.empty() || !S->try_admit(w)) {
+        S->waiting.push_back(w);
+        ++S->n_deferred;
+    }
+    return SVM_OK;
+}
+
+int svm_server_poll(void* server, int64_t ticket, svm_result_t* out) {
+    Server* S = (Server*)server;
+    if (!S || ticket < 0) return SVM_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->harvest();
+    auto f = S->failed.find(ticket);
+    if (f != S->failed.end()) return f->second;
+    auto it = S->done.find(ticket);
+    if (it == S->done.end()) return ticket < S->next_ticket ? SVM_EBUSY : SVM_EINVAL;
+    if (out) *out = it->second;
+    return it->second.status;
+}
+
+int svm_server_drain(void* server) {
+    Server* S = (Server*)server;
+    if (!S) return SVM_EINVAL;
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->harvest();
+            if (S->live.empty() && S->waiting.empty()) return SVM_OK;
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(200));
+    }
+}
+
+int svm_server_stats(void* server, int64_t* admitted, int64_t* deferred, int64_t* completed, int64_t* in_flight) {
+    Server* S = (Server*)server;
+    if (!S) return SVM_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->harvest();
+    if (admitted) *admitted = S->n_admitted;
+    if (deferred) *deferred = S->n_deferred;
+    if (completed) *completed = S->n_completed;
+    if (in_flight) *in_flight = (int64_t)S->live.size();
+    return SVM_OK;
+}
+
+int svm_server_destroy(void* server) {
+    Server* S = (Server*)server;
+    if (!S) return SVM_EINVAL;
+    if (S->shutdown) __atomic_store_n(S->shutdown, 1, __ATOMIC_RELEASE);
+    if (S->ks) (void)hipStreamSynchronize(S->ks);
+    if (S->cs) (void)hipStreamSynchronize(S->cs);
+    if (S->arena_mem) (void)hipFree(S->arena_mem);
+    if (S->head) (void)hipFree(S->head);
+    if (S->vctl) (void)hipFree(S->vctl);
+    if (S->ring) (void)hipHostFree(S->ring);
+    if (S->results) (void)hipHostFree(S->results);
+    if (S->tail) (void)hipHostFree(S->tail);
+    if (S->shutdown) (void)hipHostFree(S->shutdown);
+    if (S->ks) (void)hipStreamDestroy(S->ks);
+    if (S->cs) (void)hipStreamDestroy(S->cs);
+    delete S;
+    return SVM_OK;
+}
 
 }  // extern "C"

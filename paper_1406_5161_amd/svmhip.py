@@ -257,3 +257,52 @@ def decision_data(train, alpha: np.ndarray, beta: float, gamma: float, queries, 
         raise RuntimeError("svm_decision failed: %s" % strerror(rc))
     torch.cuda.synchronize()
     return out.cpu().numpy()
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """Continuous-batching server of training problems (svm_server_* of the C-ABI)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int):
+        h = C.c_void_p()
+        rc = lib().svm_server_create(int(hbm_budget), int(max_slots), C.byref(h))
+        if rc != SVM_OK:
+            raise RuntimeError("svm_server_create failed: %s" % strerror(rc))
+        self.h = h
+        self.keep = {}
+
+    def submit(self, prob: DeviceProblem, params: svm_params_t, alpha) -> int:
+        t = C.c_int64()
+        rc = lib().svm_server_submit(self.h, C.byref(prob.s), C.byref(params), alpha.data_ptr(), C.byref(t))
+        if rc != SVM_OK:
+            raise RuntimeError("svm_server_submit failed: %s" % strerror(rc))
+        self.keep[t.value] = (prob, alpha)
+        return t.value
+
+    def poll(self, ticket: int):
+        res = svm_result_t()
+        rc = lib().svm_server_poll(self.h, int(ticket), C.byref(res))
+        if rc == SVM_EBUSY:
+            return None
+        self.keep.pop(ticket, None)
+        return rc, res
+
+    def drain(self) -> int:
+        return lib().svm_server_drain(self.h)
+
+    def stats(self) -> dict:
+        a, d, c, f = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        lib().svm_server_stats(self.h, C.byref(a), C.byref(d), C.byref(c), C.byref(f))
+        return {"admitted": a.value, "deferred": d.value, "completed": c.value, "in_flight": f.value}
+
+    def close(self):
+        if self.h:
+            lib().svm_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
