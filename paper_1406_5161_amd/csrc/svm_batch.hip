@@ -151,6 +151,99 @@ DEV void row_dist(const BatchDesc& P, const float2* pairv, int i, int gl, int lp
     }
 }
 
+// Distances of RPT rows at once: the rows' loads are interleaved so a lane keeps several
+// rows in flight instead of walking one dependent chain after another.
+template <typename KT, int RPT>
+DEV void rows_dist(const BatchDesc& P, const float2* pairv, const int* ii, const bool* vv, int gl, int lpr,
+                   KT nuu, KT nll, KT* du2, KT* dl2) {
+    if (P.lay == LAY_DENSE) {
+        const float4* p4 = reinterpret_cast<const float4*>(pairv);
+        KT a[RPT], b[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) { a[r] = 0; b[r] = 0; }
+        for (int k4 = gl; k4 < P.dpad / 4; k4 += lpr) {
+            const float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
+            float4 v[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                v[r] = vv[r] ? reinterpret_cast<const float4*>(P.x + (size_t)ii[r] * P.dpad)[k4]
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                if constexpr (std::is_same<KT, double>::value) {
+#pragma clang fp contract(off)
+                    double t, x = a[r], y = b[r];
+                    t = (double)v[r].x - (double)q0.x; x = x + t * t;
+                    t = (double)v[r].x - (double)q0.y; y = y + t * t;
+                    t = (double)v[r].y - (double)q0.z; x = x + t * t;
+                    t = (double)v[r].y - (double)q0.w; y = y + t * t;
+                    t = (double)v[r].z - (double)q1.x; x = x + t * t;
+                    t = (double)v[r].z - (double)q1.y; y = y + t * t;
+                    t = (double)v[r].w - (double)q1.z; x = x + t * t;
+                    t = (double)v[r].w - (double)q1.w; y = y + t * t;
+                    a[r] = x; b[r] = y;
+                } else {
+                    float t, x = a[r], y = b[r];
+                    t = v[r].x - q0.x; x = fmaf(t, t, x);
+                    t = v[r].x - q0.y; y = fmaf(t, t, y);
+                    t = v[r].y - q0.z; x = fmaf(t, t, x);
+                    t = v[r].y - q0.w; y = fmaf(t, t, y);
+                    t = v[r].z - q1.x; x = fmaf(t, t, x);
+                    t = v[r].z - q1.y; y = fmaf(t, t, y);
+                    t = v[r].w - q1.z; x = fmaf(t, t, x);
+                    t = v[r].w - q1.w; y = fmaf(t, t, y);
+                    a[r] = x; b[r] = y;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            du2[r] = group_sum(a[r], lpr);
+            dl2[r] = group_sum(b[r], lpr);
+        }
+    } else {
+        int p0[RPT], p1[RPT], len = 0;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            p0[r] = vv[r] ? P.row_ptr[ii[r]] : 0;
+            p1[r] = vv[r] ? P.row_ptr[ii[r] + 1] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) len = max(len, p1[r] - p0[r]);
+        KT nn[RPT], su[RPT], sl[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) { nn[r] = 0; su[r] = 0; sl[r] = 0; }
+        for (int k = gl; k < len; k += lpr) {
+            int c[RPT];
+            float fv[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int p = p0[r] + k;
+                const bool in = p < p1[r];
+                c[r] = in ? P.col[p] : -1;
+                fv[r] = in ? (P.pattern_only ? 1.f : P.val[p]) : 0.f;
+            }
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                if (c[r] >= 0) {
+                    const float2 ul = pairv[c[r]];
+                    const KT v = (KT)fv[r];
+                    nn[r] += v * v;
+                    su[r] += v * (KT)ul.x;
+                    sl[r] += v * (KT)ul.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const KT n2 = group_sum(nn[r], lpr), s1 = group_sum(su[r], lpr), s2 = group_sum(sl[r], lpr);
+            KT a = n2 + nuu - (KT)2 * s1, b = n2 + nll - (KT)2 * s2;
+            du2[r] = a < (KT)0 ? (KT)0 : a;
+            dl2[r] = b < (KT)0 ? (KT)0 : b;
+        }
+    }
+}
+
 // Selection over the active list from (f, alpha, y) in global memory; every thread gets the result.
 DEV void select_block(const BatchDesc& P, int nact, BatchShared& sh, double& bu, int& iu, double& bl, int& il) {
     bu = INFINITY; bl = -INFINITY; iu = IDX_NONE; il = IDX_NONE;
@@ -426,17 +519,26 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
             double cbu = INFINITY, cbl = -INFINITY;
             int ciu = IDX_NONE, cil = IDX_NONE;
             int newcount = 0;
-            for (int base = 0; base < nact; base += NG) {
-                const int t = base + g;
-                const bool valid = t < nact;
-                const int i = valid ? P.act[t] : 0;
-                bool keep = false;
-                if (valid) {
-                    KT du2, dl2;
-                    row_dist<KT>(P, pairv, i, gl, lpr, nuu, nll, du2, dl2);
-                    if (gl == 0) {
-                        const double ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2);
-                        const double kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2);
+            constexpr int RPT = 4;
+            for (int base = 0; base < nact; base += NG * RPT) {
+                int ii[RPT];
+                bool vv[RPT];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const int t = base + r * NG + g;
+                    vv[r] = t < nact;
+                    ii[r] = vv[r] ? P.act[t] : 0;
+                }
+                KT du2[RPT], dl2[RPT];
+                rows_dist<KT, RPT>(P, pairv, ii, vv, gl, lpr, nuu, nll, du2, dl2);
+                bool keep[RPT];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    keep[r] = false;
+                    const int i = ii[r];
+                    if (vv[r] && gl == 0) {
+                        const double ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2[r]);
+                        const double kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2[r]);
                         double fi;
                         {
 #pragma clang fp contract(off)
@@ -453,19 +555,22 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
                             P.status[i] = st;
                             st_agent(P.alpha + i, pn.al);
                         }
-                        keep = !(do_shrink && shrink_rule(st, fi, bu, bl));
-                        if (!keep) P.status[i] = st | 8;
-                        if (keep) {
+                        keep[r] = !(do_shrink && shrink_rule(st, fi, bu, bl));
+                        if (!keep[r]) P.status[i] = st | 8;
+                        if (keep[r]) {
                             if (st_in_up(st) && better_up(fi, i, cbu, ciu)) { cbu = fi; ciu = i; }
                             if (st_in_low(st) && better_low(fi, i, cbl, cil)) { cbl = fi; cil = i; }
                         }
                     }
                 }
-                if (do_shrink) {
-                    int tot;
-                    const int pos = block_scan_keep(keep, sh.wc, tot);
-                    if (keep) P.act[newcount + pos] = i;
-                    newcount += tot;
+                if (do_shrink) {   // chunks in list order keep the compaction stable and in place
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        int tot;
+                        const int pos = block_scan_keep(keep[r], sh.wc, tot);
+                        if (keep[r]) P.act[newcount + pos] = ii[r];
+                        newcount += tot;
+                    }
                 }
             }
             block_reduce_sel_all<BB>(cbu, ciu, cbl, cil, sh.v, sh.i);

@@ -296,29 +296,35 @@ class ServeRequest:
     config: SvmConfig
 
 
-def config5(num: int = 256, rate_hz: float = 200.0, n_lo: int = 1000, n_hi: int = 50_000) -> List[ServeRequest]:
-    """Poisson stream of mixed training problems: n ~ U{n_lo..n_hi}, d in {20 dense, 128 dense,
-    300 sparse 12%}, C in {0.1, 1, 10}, gamma = 10^U(-3, 0); lazy shrinking, multi."""
+def config5_arrivals(num: int = 256, rate_hz: float = 200.0) -> np.ndarray:
+    """Poisson arrival times (s) of the serving stream: exponential gaps, first arrival at 0."""
     r = rng_for(5, 0)
     gaps = r.exponential(1.0 / rate_hz, size=num)
-    arr = np.cumsum(gaps) - gaps[0]
-    out = []
-    for j in range(num):
-        pr = rng_for(5, 1 + j)
-        n = int(pr.integers(n_lo, n_hi + 1))
-        kind = int(pr.integers(0, 3))
-        C = float([0.1, 1.0, 10.0][int(pr.integers(0, 3))])
-        gamma = float(10.0 ** pr.uniform(-3.0, 0.0))
-        if kind == 0:
-            data = gen_blobs(n, 20, pr, name="req%d_dense20" % j)
-        elif kind == 1:
-            data = gen_blobs(n, 128, pr, name="req%d_dense128" % j)
-        else:
-            data = gen_sparse_binary(n, 300, 0.12, pr, flip=0.10, name="req%d_csr300" % j)
-        cfg = SvmConfig(data.name, data, C=C, gamma=gamma, eps=1e-3, shrink_mode=SHRINK_MULTI,
-                        shrink_kind=LAZY[0], shrink_param=LAZY[1])
-        out.append(ServeRequest(j, float(arr[j]), cfg))
-    return out
+    return np.cumsum(gaps) - gaps[0]
+
+
+def config5_problem(j: int, n_lo: int = 1000, n_hi: int = 50_000) -> SvmConfig:
+    """Problem j of the serving stream: n ~ U{n_lo..n_hi}, d in {20 dense, 128 dense, 300 sparse 12%},
+    C in {0.1, 1, 10}, gamma = 10^U(-3, 0); lazy shrinking, multi."""
+    pr = rng_for(5, 1 + j)
+    n = int(pr.integers(n_lo, n_hi + 1))
+    kind = int(pr.integers(0, 3))
+    C = float([0.1, 1.0, 10.0][int(pr.integers(0, 3))])
+    gamma = float(10.0 ** pr.uniform(-3.0, 0.0))
+    if kind == 0:
+        data = gen_blobs(n, 20, pr, name="req%d_dense20" % j)
+    elif kind == 1:
+        data = gen_blobs(n, 128, pr, name="req%d_dense128" % j)
+    else:
+        data = gen_sparse_binary(n, 300, 0.12, pr, flip=0.10, name="req%d_csr300" % j)
+    return SvmConfig(data.name, data, C=C, gamma=gamma, eps=1e-3, shrink_mode=SHRINK_MULTI,
+                     shrink_kind=LAZY[0], shrink_param=LAZY[1])
+
+
+def config5(num: int = 256, rate_hz: float = 200.0, n_lo: int = 1000, n_hi: int = 50_000) -> List[ServeRequest]:
+    """Poisson stream of mixed training problems (see config5_problem)."""
+    arr = config5_arrivals(num, rate_hz)
+    return [ServeRequest(j, float(arr[j]), config5_problem(j, n_lo, n_hi)) for j in range(num)]
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}

@@ -1,0 +1,106 @@
+"""Serving comparison on the Poisson stream of mixed training problems:
+the plain one-problem-at-a-time GPU solver (svm_train, FIFO in arrival order)
+against the continuous-batching server (svm_server_*), on the same trace and
+the same eps / heuristic.  Inputs are uploaded before the clock starts;
+latency is completion minus arrival, solves/s is problems over the makespan
+(first arrival to last completion)."""
+from __future__ import annotations
+
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+from . import datagen as g
+
+
+def _make(j):
+    return g.config5_problem(j)
+
+
+def generate(num: int, workers: int = 16):
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        cfgs = list(ex.map(_make, range(num), chunksize=4))
+    return cfgs
+
+
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v), q))
+
+
+def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budget_gb: float = 64.0,
+        workers: int = 16) -> dict:
+    import torch
+    from . import svmhip as S
+    t_gen = time.perf_counter()
+    arrivals = g.config5_arrivals(num, rate_hz)
+    cfgs = generate(num, workers)
+    log("serving: generated %d problems in %.1f s" % (num, time.perf_counter() - t_gen))
+    probs = [S.to_device(c.data) for c in cfgs]
+    params = [S.params_for(c) for c in cfgs]
+    torch.cuda.synchronize()
+
+    # ---- plain loop: one problem at a time, FIFO, each waits for its arrival
+    alphas_p = [torch.zeros(c.data.n, dtype=torch.float64, device="cuda") for c in cfgs]
+    ws = None
+    lat_p, duals_p, its_p = [], [], 0
+    t0 = time.perf_counter()
+    for j, c in enumerate(cfgs):
+        now = time.perf_counter() - t0
+        if now < arrivals[j]:
+            time.sleep(arrivals[j] - now)
+        rc, r = S.svm_train(probs[j], params[j], alphas_p[j], workspace=ws)
+        assert rc in (S.SVM_OK, S.SVM_NOT_CONVERGED), S.strerror(rc)
+        lat_p.append(time.perf_counter() - t0 - arrivals[j])
+        duals_p.append(r.dual_obj)
+        its_p += r.iterations
+        if (j + 1) % 32 == 0:
+            log("serving: plain loop %d/%d done at %.1f s" % (j + 1, num, time.perf_counter() - t0))
+    span_p = time.perf_counter() - t0
+    torch.cuda.synchronize()
+
+    # ---- server: submit at arrival, poll for completions
+    alphas_s = [torch.zeros(c.data.n, dtype=torch.float64, device="cuda") for c in cfgs]
+    slots = slots or 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    done_at = [None] * num
+    res_s = [None] * num
+    with S.Server(int(budget_gb * (1 << 30)), slots) as srv:
+        tickets = {}
+        nxt = 0
+        t0 = time.perf_counter()
+        last_log = 0
+        while nxt < num or tickets:
+            now = time.perf_counter() - t0
+            while nxt < num and arrivals[nxt] <= now:
+                tickets[srv.submit(probs[nxt], params[nxt], alphas_s[nxt])] = nxt
+                nxt += 1
+            for t in list(tickets):
+                got = srv.poll(t)
+                if got is not None:
+                    j = tickets.pop(t)
+                    done_at[j] = time.perf_counter() - t0
+                    res_s[j] = got
+            done = sum(x is not None for x in done_at)
+            if done - last_log >= 32:
+                last_log = done
+                log("serving: server %d/%d done at %.1f s" % (done, num, time.perf_counter() - t0))
+            time.sleep(0.0002)
+        span_s = max(done_at)
+        stats = srv.stats()
+    torch.cuda.synchronize()
+    lat_s = [done_at[j] - arrivals[j] for j in range(num)]
+    rel = [abs(res_s[j][1].dual_obj - duals_p[j]) / max(1e-300, abs(duals_p[j])) for j in range(num)]
+    its_s = sum(res_s[j][1].iterations for j in range(num))
+    out = {
+        "problems": num, "rate_hz": rate_hz,
+        "plain": {"solves_per_s": num / span_p, "makespan_s": span_p, "p50_latency_s": _pct(lat_p, 50),
+                  "p99_latency_s": _pct(lat_p, 99), "iterations": its_p},
+        "batched": {"solves_per_s": num / span_s, "makespan_s": span_s, "p50_latency_s": _pct(lat_s, 50),
+                    "p99_latency_s": _pct(lat_s, 99), "iterations": its_s, "slots": slots, "stats": stats},
+        "speedup_solves_per_s": span_p / span_s,
+        "dual_rel_diff_max": max(rel), "dual_rel_diff_median": float(np.median(rel)),
+    }
+    log("serving: plain %.2f solves/s (p99 %.2f s), batched %.2f solves/s (p99 %.2f s), speedup %.2fx"
+        % (out["plain"]["solves_per_s"], out["plain"]["p99_latency_s"], out["batched"]["solves_per_s"],
+           out["batched"]["p99_latency_s"], out["speedup_solves_per_s"]))
+    return out
