@@ -98,7 +98,8 @@ typedef struct {
     int64_t max_iter;         /* iteration cap (> 0); reaching it returns SVM_NOT_CONVERGED */
     int32_t kernel_precision; /* SVM_KERNEL_FP32 | SVM_KERNEL_FP64 */
     uint32_t flags;           /* SVM_FLAG_* */
-    int32_t grid_blocks;      /* 0 = choose automatically; else the number of workgroups of the step */
+    int32_t grid_blocks;      /* 0 = choose automatically; else the number of workgroups of the step
+                                 (svm_train) or of the problem's team (batch / server, at most 16) */
     int32_t lanes_per_row;    /* 0 = choose automatically; CSR lanes per row (1, 2, 4, 8, 16, 32, 64) */
 } svm_params_t;
 
@@ -144,18 +145,28 @@ int svm_decision(const svm_problem_t* train, const double* alpha, double beta, d
                  const svm_problem_t* queries, double* out, int32_t kernel_precision, void* stream);
 
 /* Several independent problems in one persistent fused launch: problem p is
- * advanced by its own workgroups, problems never synchronise with each other.
- * alpha[p] (device, n_p doubles) and f[p] (device or NULL) receive the
- * solution; out[p] (host) the result.  Tile shapes come from the built-in
- * autotuner unless params[p].grid_blocks / lanes_per_row are set. */
+ * solved by its own team of workgroups (one to 16, about 3000 samples per
+ * workgroup unless params[p].grid_blocks sets it), problems never synchronise
+ * with each other.  Every problem runs the whole method of svm_train (SMO
+ * loop, shrinking, reconstruction, closing recompute) inside its team; alpha
+ * and f do not depend on the team size or on the other problems.  alpha[p]
+ * (device, n_p doubles) and f[p] (device or NULL) receive the solution; out[p]
+ * (host) the result (grid_blocks = team size, ms_step = device time of the
+ * solve).  All problems share one kernel precision.  CSR rows may hold at
+ * most 4096 nonzeros and d (dense: d rounded up to 4) at most about 1700
+ * (SVM_EUNSUPPORTED beyond).  Lanes per row come from the built-in autotuner
+ * unless params[p].lanes_per_row is set.  Returns the first non-OK status. */
 int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* params, double* const* alpha,
                     double* const* f, svm_result_t* out, void* stream);
 
 /* ---- serving: continuous batching of training problems */
 /* Create a server with a device-memory budget (bytes of solver state it may
  * keep resident) and at most max_slots problems in flight.  The server owns
- * one persistent device loop that picks up admitted problems as slots and
- * memory free up. */
+ * one persistent device loop whose workgroups pick up admitted problems (a
+ * team per problem, as in svm_train_batch) as slots and memory free up; a
+ * host thread admits waiting problems as running ones complete and stops the
+ * loop after 2 s without work (the next submit starts it again).  FP32
+ * kernel values only. */
 int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server);
 /* Queue a problem (its arrays must stay valid until the ticket completes).
  * alpha: n doubles (device) that receive the solution.  Returns a ticket. */

@@ -35,7 +35,13 @@ struct BatchShared {
     double na[SUMR];
     long long cnt;
     int ticket;
+    int rank;
     int prev_n;
+    double tsel[4];
+    int tseli[2];
+    long long tcnt;
+    int tok;
+    double tsum[6];
 };
 
 // Descriptor fields made wave-uniform (scalar registers) after the LDS broadcast.
@@ -244,11 +250,13 @@ DEV void rows_dist(const BatchDesc& P, const float2* pairv, const int* ii, const
     }
 }
 
-// Selection over the active list from (f, alpha, y) in global memory; every thread gets the result.
-DEV void select_block(const BatchDesc& P, int nact, BatchShared& sh, double& bu, int& iu, double& bl, int& il) {
+// Local selection over this member's active list from (f, alpha, y) in global memory; every
+// thread gets the result.
+DEV void select_block(const BatchDesc& P, const int32_t* act, int nact, BatchShared& sh, double& bu, int& iu,
+                      double& bl, int& il) {
     bu = INFINITY; bl = -INFINITY; iu = IDX_NONE; il = IDX_NONE;
     for (int t = threadIdx.x; t < nact; t += BB) {
-        const int i = P.act[t];
+        const int i = act[t];
         const uint8_t st = st_make(P.y[i] > 0, ld_agent(P.alpha + i), P.C);
         const double fi = P.f[i];
         if (st_in_up(st) && better_up(fi, i, bu, iu)) { bu = fi; iu = i; }
@@ -256,19 +264,174 @@ DEV void select_block(const BatchDesc& P, int nact, BatchShared& sh, double& bu,
     }
     block_reduce_sel_all<BB>(bu, iu, bl, il, sh.v, sh.i);
     __syncthreads();
-    if (iu == IDX_NONE) iu = -1;
-    if (il == IDX_NONE) il = -1;
 }
 
-// Stable compaction over 0..n-1: list = ids with pred(i) (0: shrunk, i.e. status bit 3 set;
-// 1: alpha > 0, with coefficient alpha * y).  Returns the count (all threads).
+// ---- team exchanges: the B workgroups of one problem publish tag-validated records
+// (high half of each 64-bit word = exchange sequence number) and read each other's.
+
+// Watchdogs (device wall clock, 100 MHz): the first exchange of a problem waits for the team to
+// gather (members start as workgroups finish earlier problems); later exchanges wait only for
+// members doing the same step.  An expired wait ends the solve with SVM_EABORT.
+constexpr unsigned long long TEAM_GATHER_TICKS = 120ull * 100 * 1000 * 1000;
+constexpr unsigned long long TEAM_WAIT_TICKS = 30ull * 100 * 1000 * 1000;
+
+struct TeamSel {
+    double bu, bl, au, al;
+    int iu, il;
+    long long cnt;
+    int ok;
+};
+
+// Wave 0 of the calling workgroup waits for all B records of exchange `seq` and returns them
+// decoded in lanes < B; false if the watchdog fired.
+DEV bool team_read(const unsigned long long* trec, int B, unsigned seq, unsigned* v,
+                   unsigned long long spin_limit) {
+    const int lane = threadIdx.x & 63;
+    bool ok = true;
+    if (lane < B) {
+        const unsigned long long* w = trec + ((size_t)(seq & 1) * B + lane) * 16;
+        const unsigned long long t0 = wall_clock64();
+        while ((unsigned)(ld_agent(w + REC_WORDS - 1) >> 32) != seq) {
+            if (wall_clock64() - t0 > spin_limit) { ok = false; break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        for (; ok;) {
+            bool all = true;
+#pragma unroll
+            for (int k = 0; k < REC_WORDS; ++k) {
+                const unsigned long long x = ld_agent(w + k);
+                v[k] = (unsigned)(x & 0xffffffffull);
+                all = all && (unsigned)(x >> 32) == seq;
+            }
+            if (all) break;
+            if (wall_clock64() - t0 > spin_limit) { ok = false; break; }
+        }
+    }
+    return __all(ok);
+}
+
+DEV void team_write(unsigned long long* trec, int B, int rank, unsigned seq, const unsigned* v) {
+    unsigned long long* w = trec + ((size_t)(seq & 1) * B + rank) * 16;
+    const unsigned long long TAG = (unsigned long long)seq << 32;
+#pragma unroll
+    for (int k = 0; k < REC_WORDS; ++k) st_agent(w + k, TAG | v[k]);
+}
+
+DEV void pack_d(unsigned* v, int k, double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    v[k] = (unsigned)(b & 0xffffffffull);
+    v[k + 1] = (unsigned)(b >> 32);
+}
+DEV double unpack_d(const unsigned* v, int k) {
+    return __longlong_as_double((long long)(((unsigned long long)v[k + 1] << 32) | v[k]));
+}
+
+// Merge the members' candidates (called by every thread; thread 0 holds this member's values).
+DEV TeamSel team_select(const BatchDesc& P, int rank, unsigned seq, double bu, int iu, double au, double bl,
+                        int il, double al, long long cnt, BatchShared& sh) {
+    const int tid = threadIdx.x;
+    TeamSel r;
+    if (P.team == 1) {
+        if (tid == 0) {
+            sh.tsel[0] = bu; sh.tsel[1] = bl; sh.tsel[2] = au; sh.tsel[3] = al;
+            sh.tseli[0] = iu; sh.tseli[1] = il; sh.tcnt = cnt; sh.tok = 1;
+        }
+    } else {
+        if (tid == 0) {
+            unsigned v[REC_WORDS];
+            pack_d(v, 0, bu); pack_d(v, 2, bl); pack_d(v, 4, au); pack_d(v, 6, al);
+            v[8] = (unsigned)iu; v[9] = (unsigned)il;
+            v[10] = (unsigned)(cnt & 0xffffffffll); v[11] = (unsigned)((unsigned long long)cnt >> 32);
+            v[12] = v[13] = v[14] = 0;
+            team_write(P.trec, P.team, rank, seq, v);
+        }
+        if (tid < 64) {
+            unsigned v[REC_WORDS];
+            const bool ok = team_read(P.trec, P.team, seq, v, seq == 1 ? TEAM_GATHER_TICKS : TEAM_WAIT_TICKS);
+            const int lane = tid;
+            double xbu = INFINITY, xbl = -INFINITY, xau = 0.0, xal = 0.0;
+            int xiu = IDX_NONE, xil = IDX_NONE;
+            long long xc = 0;
+            if (lane < P.team && ok) {
+                xbu = unpack_d(v, 0); xbl = unpack_d(v, 2); xau = unpack_d(v, 4); xal = unpack_d(v, 6);
+                xiu = (int)v[8]; xil = (int)v[9];
+                xc = (long long)(((unsigned long long)v[11] << 32) | v[10]);
+            }
+            const int myiu = xiu, myil = xil;
+            const long long tot = wave_sum(xc);
+            wave_reduce_sel(xbu, xiu, xbl, xil);
+            if (lane < P.team && myiu == xiu && xiu != IDX_NONE) sh.tsel[2] = xau;
+            if (lane < P.team && myil == xil && xil != IDX_NONE) sh.tsel[3] = xal;
+            if (lane == 0) {
+                sh.tsel[0] = xbu; sh.tsel[1] = xbl; sh.tseli[0] = xiu; sh.tseli[1] = xil; sh.tcnt = tot;
+                sh.tok = ok ? 1 : 0;
+                if (xiu == IDX_NONE) sh.tsel[2] = 0.0;
+                if (xil == IDX_NONE) sh.tsel[3] = 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    r.bu = sh.tsel[0]; r.bl = sh.tsel[1]; r.au = sh.tsel[2]; r.al = sh.tsel[3];
+    r.iu = sh.tseli[0] == IDX_NONE ? -1 : sh.tseli[0];
+    r.il = sh.tseli[1] == IDX_NONE ? -1 : sh.tseli[1];
+    r.cnt = sh.tcnt;
+    r.ok = sh.tok;
+    __syncthreads();
+    return r;
+}
+
+// Sum 6 doubles over the team (thread 0 holds this member's values); every thread gets the totals.
+// With fence = true the exchange also publishes every global write made before it (alpha of the
+// pair rows) to the other members.
+DEV bool team_sum(const BatchDesc& P, int rank, unsigned seq, const double* x6, double* out6, bool fence,
+                  BatchShared& sh) {
+    const int tid = threadIdx.x;
+    if (P.team == 1) {
+        if (tid == 0) {
+            for (int k = 0; k < 6; ++k) sh.tsum[k] = x6[k];
+            sh.tok = 1;
+        }
+    } else {
+        if (fence) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) {
+            unsigned v[REC_WORDS];
+            for (int k = 0; k < 6; ++k) pack_d(v, 2 * k, x6[k]);
+            v[12] = v[13] = v[14] = 0;
+            team_write(P.trec, P.team, rank, seq, v);
+        }
+        if (tid < 64) {
+            unsigned v[REC_WORDS];
+            const bool ok = team_read(P.trec, P.team, seq, v, TEAM_WAIT_TICKS);
+            double t[6] = {0, 0, 0, 0, 0, 0};
+            if (tid < P.team && ok)
+                for (int k = 0; k < 6; ++k) t[k] = unpack_d(v, 2 * k);
+            // sum in member order for the same result in every member
+            for (int k = 0; k < 6; ++k) {
+                double acc = 0.0;
+                for (int m = 0; m < P.team; ++m) acc += __shfl(t[k], m);
+                if (tid == 0) sh.tsum[k] = acc;
+            }
+            if (tid == 0) sh.tok = ok ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (fence && P.team > 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int k = 0; k < 6; ++k) out6[k] = sh.tsum[k];
+    const bool ok = sh.tok != 0;
+    __syncthreads();
+    return ok;
+}
+
+// Stable compaction over ids lo..hi-1: list = ids with pred(i) (0: shrunk, i.e. status bit 3
+// set; 1: alpha > 0, with coefficient alpha * y).  Returns the count (all threads).
 template <int PRED>
-DEV int compact_block(const BatchDesc& P, int n, int32_t* list, double* coef, BatchShared& sh) {
+DEV int compact_block(const BatchDesc& P, int lo, int hi, int32_t* list, double* coef, BatchShared& sh) {
     int out = 0;
-    for (int base = 0; base < n; base += BB) {
+    for (int base = lo; base < hi; base += BB) {
         const int i = base + threadIdx.x;
         bool k = false;
-        if (i < n) {
+        if (i < hi) {
             if (PRED == 0) k = (P.status[i] & 8) != 0;
             else k = ld_agent(P.alpha + i) > 0.0;
         }
@@ -286,7 +449,9 @@ DEV int compact_block(const BatchDesc& P, int n, int32_t* list, double* coef, Ba
 
 // f[a] = sum_j coef_j K(x_a, x_{z_j}) - y_a for the rows in `rows` (or 0..na-1), block-local (Alg. 6).
 template <typename KT>
-__device__ __attribute__((noinline)) void kernel_sum_block(const BatchDesc& P, const int32_t* rows, int na, int nz, float* tile, BatchShared& sh) {
+__device__ __attribute__((noinline)) void kernel_sum_block(const BatchDesc& P, const int32_t* rows, int row0, int na,
+                                                          const int32_t* lz, const double* lcoef, int nz, float* tile,
+                                                          BatchShared& sh) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const bool dense = P.lay == LAY_DENSE;
     const int W = dense ? P.dpad : P.d;
@@ -298,12 +463,12 @@ __device__ __attribute__((noinline)) void kernel_sum_block(const BatchDesc& P, c
         if (dense) {
             for (int e = tid; e < nr * W; e += BB) {
                 const int r = e / W, k = e % W;
-                const int a = rows ? rows[r0 + r] : r0 + r;
+                const int a = rows ? rows[r0 + r] : row0 + r0 + r;
                 tile[e] = P.x[(size_t)a * P.dpad + k];
             }
         } else {
             for (int r = 0; r < nr; ++r) {
-                const int a = rows ? rows[r0 + r] : r0 + r;
+                const int a = rows ? rows[r0 + r] : row0 + r0 + r;
                 for (int p = P.row_ptr[a] + tid; p < P.row_ptr[a + 1]; p += BB)
                     tile[r * W + P.col[p]] = P.pattern_only ? 1.f : P.val[p];
             }
@@ -325,8 +490,8 @@ __device__ __attribute__((noinline)) void kernel_sum_block(const BatchDesc& P, c
 #pragma unroll
         for (int r = 0; r < SUMR; ++r) acc[r] = 0.0;
         for (int jb = tid; jb < nz; jb += BB) {
-            const int j = P.list_z[jb];
-            const double cj = P.coef[jb];
+            const int j = lz[jb];
+            const double cj = lcoef[jb];
             KT dist[SUMR];
 #pragma unroll
             for (int r = 0; r < SUMR; ++r) dist[r] = 0;
@@ -386,47 +551,76 @@ __device__ __attribute__((noinline)) void kernel_sum_block(const BatchDesc& P, c
         if (tid < nr) {
             double v = 0.0;
             for (int w = 0; w < BNW; ++w) v += sh.red[w][tid];
-            const int a = rows ? rows[r0 + tid] : r0 + tid;
+            const int a = rows ? rows[r0 + tid] : row0 + r0 + tid;
             P.f[a] = v - (P.y[a] > 0 ? 1.0 : -1.0);
         }
         __syncthreads();
     }
 }
 
-// The whole solve of one problem by the calling workgroup.
+// One member (rank) of the team of P.team workgroups solving problem P.  Member b owns rows
+// [n b / B, n (b+1) / B); the members run the same driver, take the same decisions from the
+// merged selections, and meet only in team exchanges.
 template <typename KT>
-DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
+DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
     const BatchDesc& P = sh.P;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int n = P.n;
+    const int n = P.n, B = P.team, rank = sh.rank;
+    const int seg0 = (int)(((long long)n * rank) / B), seg1 = (int)(((long long)n * (rank + 1)) / B);
     const int lpr = P.lpr;
     const int NG = BB / lpr, g = tid / lpr, gl = tid % lpr;
     const double C = P.C;
     const bool dense = P.lay == LAY_DENSE;
+    int32_t* act = P.act + seg0;
+    int32_t* lw = P.list_w + seg0;
+    int32_t* lz = P.list_z + (size_t)rank * n;
+    double* lcoef = P.coef + (size_t)rank * n;
     float2* pairv = reinterpret_cast<float2*>(dyn);
     const int pair_entries = dense ? P.dpad : P.d;
     int* prev_cols = reinterpret_cast<int*>(dyn + sizeof(float2) * (size_t)pair_entries);
     const size_t tile_off = (sizeof(float2) * (size_t)pair_entries + sizeof(int) * 2 * 4096 + 15) & ~(size_t)15;
     float* tile = reinterpret_cast<float*>(dyn + tile_off);
     const unsigned long long t_start = wall_clock64();
+    unsigned seq = 1;
+    bool alive = true;
 
-    // initial state: alpha = 0, f = -y, everything active (status bit 3 = shrunk)
-    for (int i = tid; i < n; i += BB) {
+    // initial state of this member's rows: alpha = 0, f = -y, active (status bit 3 = shrunk)
+    for (int i = seg0 + tid; i < seg1; i += BB) {
         const bool yp = P.y[i] > 0;
         st_agent(P.alpha + i, 0.0);
         P.f[i] = yp ? -1.0 : 1.0;
         P.status[i] = st_make(yp, 0.0, C);
-        P.act[i] = i;
+        act[i - seg0] = i;
     }
     if (!dense)
         for (int k = tid; k < P.d; k += BB) pairv[k] = make_float2(0.f, 0.f);
     if (tid == 0) sh.prev_n = 0;
     __syncthreads();
 
-    int nact = n;
-    double bu, bl;
+    int nact = seg1 - seg0;
+    long long nact_total = n;
+    double bu, bl, au = 0.0, al = 0.0;
     int iu, il;
-    select_block(P, nact, sh, bu, iu, bl, il);
+    // merge this member's candidates; (ju, aju), (jl, ajl): rows whose alpha this workgroup has
+    // just changed, with their new values (the only alphas not yet settled in memory)
+    auto merge = [&](double cbu, int ciu, double cbl, int cil, long long cnt, int ju, double aju, int jl,
+                     double ajl) {
+        double cau = 0.0, cal = 0.0;
+        if (tid == 0) {
+            if (ciu != IDX_NONE) cau = ciu == ju ? aju : ciu == jl ? ajl : ld_agent(P.alpha + ciu);
+            if (cil != IDX_NONE) cal = cil == ju ? aju : cil == jl ? ajl : ld_agent(P.alpha + cil);
+        }
+        const TeamSel t = team_select(P, rank, seq++, cbu, ciu, cau, cbl, cil, cal, cnt, sh);
+        bu = t.bu; bl = t.bl; au = t.au; al = t.al; iu = t.iu; il = t.il;
+        if (!t.ok) alive = false;
+        return t.cnt;
+    };
+    {
+        double cbu, cbl;
+        int ciu, cil;
+        select_block(P, act, nact, sh, cbu, ciu, cbl, cil);
+        merge(cbu, ciu, cbl, cil, nact, -1, 0.0, -1, 0.0);
+    }
     bool shrinking = P.shrink_mode != SVM_SHRINK_NONE;
     double thr = shrinking ? 20.0 * P.eps : 2.0 * P.eps;
     const long long H = shrinking ? P.H : 0;
@@ -434,11 +628,35 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
     int n_recon = 0, rechecks = 0, status = SVM_OK;
     const bool final_recompute = P.kprec == SVM_KERNEL_FP32 && !(P.flags & SVM_FLAG_NO_FINAL_RECOMPUTE);
 
-    for (;;) {
+    // f of this member's shrunk rows (all its rows when `all`) from the current support vectors
+    auto rebuild = [&](bool all) {
+        const double zero6[6] = {0, 0, 0, 0, 0, 0};
+        double t6[6];
+        if (!team_sum(P, rank, seq++, zero6, t6, true, sh)) { alive = false; return; }   // publishes alpha
+        const int nz = compact_block<1>(P, 0, n, lz, lcoef, sh);
+        if (all) {
+            kernel_sum_block<KT>(P, nullptr, seg0, seg1 - seg0, lz, lcoef, nz, tile, sh);
+        } else {
+            const int nw = compact_block<0>(P, seg0, seg1, lw, nullptr, sh);
+            if (nw > 0) kernel_sum_block<KT>(P, lw, 0, nw, lz, lcoef, nz, tile, sh);
+        }
+        for (int i = seg0 + tid; i < seg1; i += BB) {
+            P.status[i] &= 7;
+            act[i - seg0] = i;
+        }
+        __syncthreads();
+        nact = seg1 - seg0;
+        nact_total = n;
+        double cbu, cbl;
+        int ciu, cil;
+        select_block(P, act, nact, sh, cbu, ciu, cbl, cil);
+        merge(cbu, ciu, cbl, cil, nact, -1, 0.0, -1, 0.0);
+    };
+
+    while (alive) {
         // ---- SMO iterations of this phase
-        while (bl - bu > thr) {
+        while (alive && bl - bu > thr) {
             if (iter >= P.max_iter) { status = SVM_NOT_CONVERGED; break; }
-            const double au = ld_agent(P.alpha + iu), al = ld_agent(P.alpha + il);
             const int yu = P.y[iu] > 0 ? 1 : -1, yl = P.y[il] > 0 ? 1 : -1;
             if (dense) {
                 const float* xu = P.x + (size_t)iu * P.dpad;
@@ -446,7 +664,7 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
                 for (int k = tid; k < P.dpad; k += BB) pairv[k] = make_float2(xu[k], xl[k]);
                 __syncthreads();
                 if (tid == 0) {
-                    double s;
+                    double sk;
                     if constexpr (std::is_same<KT, double>::value) {
 #pragma clang fp contract(off)
                         double a = 0.0;
@@ -454,16 +672,16 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
                             const double t = (double)pairv[k].x - (double)pairv[k].y;
                             a = a + t * t;
                         }
-                        s = exp(-P.gamma * a);
+                        sk = exp(-P.gamma * a);
                     } else {
                         float a = 0.f;
                         for (int k = 0; k < P.dpad; ++k) {
                             const float t = pairv[k].x - pairv[k].y;
                             a = fmaf(t, t, a);
                         }
-                        s = (double)expf(-(float)P.gamma * a);
+                        sk = (double)expf(-(float)P.gamma * a);
                     }
-                    sh.pair[0] = s;
+                    sh.pair[0] = sk;
                 }
             } else {
                 const int pu0 = P.row_ptr[iu], pu1 = P.row_ptr[iu + 1];
@@ -512,7 +730,7 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
             const KT gam = (KT)P.gamma;
             const KT nuu = dense ? (KT)0 : (KT)sh.pair[1], nll = dense ? (KT)0 : (KT)sh.pair[2];
             bool do_shrink = false;
-            if (H > 0) {
+            if (shrinking) {
                 --counter;
                 do_shrink = counter == 0;
             }
@@ -527,7 +745,7 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
                 for (int r = 0; r < RPT; ++r) {
                     const int t = base + r * NG + g;
                     vv[r] = t < nact;
-                    ii[r] = vv[r] ? P.act[t] : 0;
+                    ii[r] = vv[r] ? act[t] : 0;
                 }
                 KT du2[RPT], dl2[RPT];
                 rows_dist<KT, RPT>(P, pairv, ii, vv, gl, lpr, nuu, nll, du2, dl2);
@@ -568,39 +786,29 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
                     for (int r = 0; r < RPT; ++r) {
                         int tot;
                         const int pos = block_scan_keep(keep[r], sh.wc, tot);
-                        if (keep[r]) P.act[newcount + pos] = ii[r];
+                        if (keep[r]) act[newcount + pos] = ii[r];
                         newcount += tot;
                     }
                 }
             }
             block_reduce_sel_all<BB>(cbu, ciu, cbl, cil, sh.v, sh.i);
             __syncthreads();
-            bu = cbu; bl = cbl;
-            iu = ciu == IDX_NONE ? -1 : ciu;
-            il = cil == IDX_NONE ? -1 : cil;
+            if (do_shrink) nact = newcount;
+            const long long tot = merge(cbu, ciu, cbl, cil, nact, iu, pn.au, il, pn.al);
             if (do_shrink) {
-                shrunk += nact - newcount;
-                nact = newcount;
+                shrunk += nact_total - tot;
+                nact_total = tot;
                 ++passes;
-                counter = nact < H ? nact : H;
+                counter = tot < H ? tot : H;
                 if (counter < 1) counter = 1;
             }
             ++iter;
         }
-        if (status != SVM_OK) break;
+        if (!alive || status != SVM_OK) break;
         if (shrinking) {
-            // the active set meets the tolerance: rebuild f of the shrunk samples (Alg. 6)
-            const int nw = compact_block<0>(P, n, P.list_w, nullptr, sh);
-            const int nz = compact_block<1>(P, n, P.list_z, P.coef, sh);
-            if (nw > 0) kernel_sum_block<KT>(P, P.list_w, nw, nz, tile, sh);
-            for (int i = tid; i < n; i += BB) {
-                P.status[i] &= 7;
-                P.act[i] = i;
-            }
-            __syncthreads();
-            nact = n;
+            rebuild(false);                     // the active set meets the tolerance: Alg. 6
             ++n_recon;
-            select_block(P, nact, sh, bu, iu, bl, il);
+            if (!alive) break;
             if (bl - bu > 2.0 * P.eps) {
                 thr = 2.0 * P.eps;
                 if (P.shrink_mode == SVM_SHRINK_SINGLE) shrinking = false;
@@ -610,9 +818,8 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
         }
         if (final_recompute && rechecks < 2) {
             ++rechecks;
-            const int nz = compact_block<1>(P, n, P.list_z, P.coef, sh);
-            kernel_sum_block<KT>(P, nullptr, n, nz, tile, sh);
-            select_block(P, nact, sh, bu, iu, bl, il);
+            rebuild(true);
+            if (!alive) break;
             if (bl - bu > 2.0 * P.eps) {
                 thr = 2.0 * P.eps;
                 counter = H;
@@ -621,50 +828,67 @@ DEV void solve_one(BatchShared& sh, unsigned char* dyn) {
         }
         break;
     }
-    if (status == SVM_NOT_CONVERGED && nact < n) {
-        const int nw = compact_block<0>(P, n, P.list_w, nullptr, sh);
-        const int nz = compact_block<1>(P, n, P.list_z, P.coef, sh);
-        if (nw > 0) kernel_sum_block<KT>(P, P.list_w, nw, nz, tile, sh);
-        for (int i = tid; i < n; i += BB) {
-            P.status[i] &= 7;
-            P.act[i] = i;
+    if (alive && status == SVM_NOT_CONVERGED && nact_total < n) {
+        rebuild(false);
+        ++n_recon;
+    }
+    // ---- threshold and summary over the team
+    double x6[6] = {0, 0, 0, 0, 0, 0}, s6[6];
+    if (alive) {
+        double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0;
+        for (int i = seg0 + tid; i < seg1; i += BB) {
+            const double a = ld_agent(P.alpha + i);
+            const double yi = P.y[i] > 0 ? 1.0 : -1.0;
+            if (a > 0.0 && a < C) { v0 += P.f[i]; v1 += 1.0; }
+            v2 += a;
+            v3 += a * yi * (P.f[i] + yi);
+            if (a > 0.0) v4 += 1.0;
+            if (a >= C) v5 += 1.0;
+        }
+        v0 = wave_sum(v0); v1 = wave_sum(v1); v2 = wave_sum(v2);
+        v3 = wave_sum(v3); v4 = wave_sum(v4); v5 = wave_sum(v5);
+        if (lane == 0) {
+            sh.red[wid][0] = v0; sh.red[wid][1] = v1; sh.red[wid][2] = v2;
+            sh.red[wid][3] = v3; sh.red[wid][4] = v4; sh.red[wid][5] = v5;
         }
         __syncthreads();
-        nact = n;
-        ++n_recon;
-        select_block(P, nact, sh, bu, iu, bl, il);
+        if (tid == 0)
+            for (int w = 0; w < BNW; ++w)
+                for (int k = 0; k < 6; ++k) x6[k] += sh.red[w][k];
+        __syncthreads();
+        if (!team_sum(P, rank, seq++, x6, s6, true, sh)) alive = false;
     }
-    // ---- threshold and summary
-    double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0;
-    for (int i = tid; i < n; i += BB) {
-        const double a = ld_agent(P.alpha + i);
-        const double yi = P.y[i] > 0 ? 1.0 : -1.0;
-        if (a > 0.0 && a < C) { v0 += P.f[i]; v1 += 1.0; }
-        v2 += a;
-        v3 += a * yi * (P.f[i] + yi);
-        if (a > 0.0) v4 += 1.0;
-        if (a >= C) v5 += 1.0;
+    // ---- completion: every member posts an acknowledgement and leaves; rank 0 waits for all of
+    // them before it publishes the result (after which the host may reuse the team records)
+    if (P.team > 1) {
+        if (tid == 0) {
+            unsigned v[REC_WORDS];
+            for (int k = 0; k < REC_WORDS; ++k) v[k] = 0;
+            team_write(P.trec, P.team, rank, seq, v);
+        }
+        if (rank == 0) {                  // rank is uniform in the workgroup
+            if (tid == 0) sh.tok = 1;
+            __syncthreads();
+            if (tid < 64) {
+                unsigned v[REC_WORDS];
+                const bool ok = team_read(P.trec, P.team, seq, v, TEAM_WAIT_TICKS);
+                if (tid == 0 && !ok) sh.tok = 0;
+            }
+            __syncthreads();
+            if (!sh.tok) alive = false;
+        }
     }
-    v0 = wave_sum(v0); v1 = wave_sum(v1); v2 = wave_sum(v2);
-    v3 = wave_sum(v3); v4 = wave_sum(v4); v5 = wave_sum(v5);
-    if (lane == 0) {
-        sh.red[wid][0] = v0; sh.red[wid][1] = v1; sh.red[wid][2] = v2;
-        sh.red[wid][3] = v3; sh.red[wid][4] = v4; sh.red[wid][5] = v5;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double s[6] = {0, 0, 0, 0, 0, 0};
-        for (int w = 0; w < BNW; ++w)
-            for (int k = 0; k < 6; ++k) s[k] += sh.red[w][k];
+    if (rank == 0 && tid == 0) {
         BatchResult* R = P.res;
-        const double beta = s[1] > 0 ? s[0] / s[1] : 0.5 * (bu + bl);
+        if (!alive) status = SVM_EABORT;
+        const double beta = alive && s6[1] > 0 ? s6[0] / s6[1] : 0.5 * (bu + bl);
         __hip_atomic_store(&R->beta, beta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(&R->b_up, bu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(&R->b_low, bl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&R->dual_obj, s[2] - 0.5 * s[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->dual_obj, alive ? s6[2] - 0.5 * s6[3] : 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(&R->iterations, iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&R->n_sv, (int32_t)s[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&R->n_bsv, (int32_t)s[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->n_sv, alive ? (int32_t)s6[4] : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&R->n_bsv, alive ? (int32_t)s6[5] : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(&R->n_recon, n_recon, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(&R->status, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(&R->shrink_passes, passes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -682,32 +906,45 @@ __global__ __launch_bounds__(BB) void smo_batch_kernel(BatchArgs A) {
     __shared__ BatchShared sh;
     const int tid = threadIdx.x;
     for (;;) {
-        // ---- take a ticket; wait until its descriptor is published or the host stops the loop
+        // ---- take a worker ticket (a problem and a rank in its team); wait until it is
+        // published or the host stops the loop
         if (tid == 0) {
             const int t = atomicAdd(A.head, 1);
             int ok = 0;
             if (A.fixed_tail > 0) {
                 ok = t < A.fixed_tail;
             } else {
-                const unsigned long long t0 = wall_clock64();
+                // Only the workgroup holding the lowest unpublished ticket (the leader) polls the
+                // host-written tail and shutdown flag; it mirrors them into device memory, where
+                // the other waiting workgroups poll.
                 for (;;) {
-                    const int tail = __hip_atomic_load(A.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-                    if (t < tail) { ok = 1; break; }
-                    if (__hip_atomic_load(A.shutdown, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) {
-                        // published before the stop request?
-                        ok = t < __hip_atomic_load(A.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-                        break;
+                    const int m = __hip_atomic_load(A.mirror, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (t < m) { ok = 1; break; }
+                    if (__hip_atomic_load(A.mirror + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) break;
+                    if (t == m) {
+                        const int tail = __hip_atomic_load(A.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                        if (tail > m) {
+                            __hip_atomic_store(A.mirror, tail, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                            continue;
+                        }
+                        if (__hip_atomic_load(A.shutdown, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) {
+                            __hip_atomic_store(A.mirror + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
                     }
-                    if (wall_clock64() - t0 > A.idle_limit) break;
                     __builtin_amdgcn_s_sleep(127);
                 }
             }
             sh.ticket = ok ? t : -1;
-            if (ok) sh.P = A.descs[t & (A.capacity - 1)];
+            if (ok) {
+                const int2 tk = A.tickets[t & (A.tcapacity - 1)];
+                sh.rank = tk.y;
+                sh.P = A.descs[tk.x & (A.capacity - 1)];
+            }
         }
         __syncthreads();
         if (sh.ticket < 0) break;
-        solve_one<KT>(sh, dyn);
+        solve_team<KT>(sh, dyn);
     }
 }
 

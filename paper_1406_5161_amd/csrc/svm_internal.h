@@ -171,7 +171,7 @@ int device_cu_count();
 
 namespace svm {
 
-// ---- batched / serving solver: one workgroup solves one whole problem
+// ---- batched / serving solver: a team of workgroups solves one problem
 
 constexpr int BATCH_BLOCK = 512;
 
@@ -198,24 +198,29 @@ struct BatchDesc {
     long long H, max_iter;
     uint32_t flags;
     int32_t pad;
+    int32_t team;                        // workgroups solving this problem together
+    int32_t pad2;
+    unsigned long long* trec;            // team exchange records [2][team][16], zeroed before the start
     // per-problem device workspace
     double* alpha;
     double* f;
     uint8_t* status;
     int32_t* act;
     int32_t* list_w;
-    int32_t* list_z;
-    double* coef;
+    int32_t* list_z;                     // [team][n]: each member's support-vector list
+    double* coef;                        // [team][n]
     BatchResult* res;                    // device or pinned host memory
 };
 
 struct BatchArgs {
     const BatchDesc* descs;              // descriptor ring (device or pinned host)
     int32_t capacity;                    // ring size (power of two)
+    int32_t tcapacity;                   // ticket ring size (power of two)
+    const int2* tickets;                 // worker ticket -> (descriptor slot, rank in the team)
     int32_t* head;                       // device counter: next ticket
-    const int32_t* tail;                 // number of published descriptors (host-written when serving)
-    const int32_t* shutdown;             // host sets 1 to stop the loop once the queue is drained
-    unsigned long long idle_limit;       // watchdog: wall-clock ticks a workgroup may wait for work
+    const int32_t* tail;                 // number of published tickets (host-written when serving)
+    const int32_t* shutdown;             // host sets 1 to stop the loop; set only when no ticket waits
+    int32_t* mirror;                     // device [2]: tail and shutdown as last seen by the leader
     int32_t fixed_tail;                  // > 0: a fixed batch (tail is this value, no polling)
     int32_t pad;
 };

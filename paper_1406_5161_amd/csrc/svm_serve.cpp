@@ -1,13 +1,22 @@
 // svm_serve.cpp -- batched training (svm_train_batch) and the serving loop
 // (svm_server_*): continuous batching of SVM training problems on one GPU.
 //
-// Both run the persistent batched kernel of svm_batch.hip, in which one
-// workgroup solves one whole problem.  The batch entry point hands it a fixed
-// list; the server keeps the kernel running and publishes problems into a
-// descriptor ring in pinned host memory as they are admitted.  Admission
-// needs a free slot (at most max_slots problems in flight) and room for the
-// problem's solver state in the server's device-memory arena; otherwise the
-// problem waits in a FIFO and is admitted when a running one completes.
+// Both run the persistent batched kernel of svm_batch.hip, in which a team of
+// one to 16 workgroups solves one problem (the team size grows with n).  Each
+// workgroup takes worker tickets; ticket t names a descriptor slot and a rank
+// in that problem's team, and the tickets of one problem are consecutive.  The
+// batch entry point hands the kernel a fixed ticket table; the server keeps the
+// kernel running and publishes descriptors and tickets into rings in pinned
+// host memory as problems are admitted.  Admission needs a free slot (at most
+// max_slots problems in flight) and room for the problem's solver state in the
+// server's device-memory arena; otherwise the problem waits in a FIFO and is
+// admitted when a running one completes.  A monitor thread admits waiting
+// problems as others complete and parks the kernel after 2 s without work.
+//
+// Progress of teams: tickets are taken in order and a problem's tickets are
+// consecutive, so the oldest partly taken problem always has its missing
+// members among the workgroups that finish the problems before it; with at
+// least as many workgroups as the largest team, every team fills.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,10 +59,10 @@ int tune_lanes_per_row(const svm_problem_t* p, double avg_nnz, int kprec, int re
 }
 
 struct ProbBytes {
-    size_t x, f, status, act, lw, lz, coef, total;
+    size_t x, f, status, act, lw, lz, coef, trec, total;
 };
 
-ProbBytes prob_bytes(const svm_problem_t* p, bool need_f) {
+ProbBytes prob_bytes(const svm_problem_t* p, bool need_f, int team) {
     ProbBytes b{};
     const size_t n = (size_t)p->n;
     size_t o = 0;
@@ -63,8 +72,9 @@ ProbBytes prob_bytes(const svm_problem_t* p, bool need_f) {
     b.status = take(n);
     b.act = take(sizeof(int32_t) * n);
     b.lw = take(sizeof(int32_t) * n);
-    b.lz = take(sizeof(int32_t) * n);
-    b.coef = take(sizeof(double) * n);
+    b.lz = take(sizeof(int32_t) * n * team);
+    b.coef = take(sizeof(double) * n * team);
+    b.trec = take(sizeof(unsigned long long) * 2 * 16 * team);
     b.total = o;
     return b;
 }
@@ -90,6 +100,15 @@ int check_batch_problem(const svm_problem_t* p, const svm_params_t* q) {
     return SVM_OK;
 }
 
+// Team size: the requested one (params.grid_blocks), else about 3000 rows per workgroup; at most
+// 16 and at most the workgroups of the launch.
+int team_size(int n, int workers, int requested) {
+    int b = requested > 0 ? requested : (n + 2999) / 3000;
+    if (b > 16) b = 16;
+    if (b > workers) b = workers;
+    return b < 1 ? 1 : b;
+}
+
 int64_t shrink_h(const svm_params_t* q, int n) {
     if (q->shrink_mode == SVM_SHRINK_NONE) return 0;
     double h = q->shrink_kind == SVM_KIND_FIXED ? q->shrink_param : std::ceil(q->shrink_param * (double)n);
@@ -97,8 +116,8 @@ int64_t shrink_h(const svm_params_t* q, int n) {
 }
 
 // Validate on the device and fill a descriptor; `ws` holds prob_bytes(p) bytes.
-int prepare(const svm_problem_t* p, const svm_params_t* q, double* alpha, double* f_user, unsigned char* ws,
-            BatchResult* res, Ctl* vctl, hipStream_t s, BatchDesc* D) {
+int prepare(const svm_problem_t* p, const svm_params_t* q, int team, double* alpha, double* f_user,
+            unsigned char* ws, BatchResult* res, Ctl* vctl, hipStream_t s, BatchDesc* D) {
     hipError_t e = hipMemsetAsync(vctl, 0, sizeof(Ctl), s);
     if (e == hipSuccess)
         e = launch_validate(p->n, p->d, p->layout, p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR, p->row_ptr,
@@ -114,7 +133,7 @@ int prepare(const svm_problem_t* p, const svm_params_t* q, double* alpha, double
     if (h.err & 2) return SVM_ENONFINITE;
     if (h.n_pos == 0 || h.n_neg == 0) return SVM_EONECLASS;
     if (p->layout == SVM_CSR && h.max_row_nnz > 4096) return SVM_EUNSUPPORTED;
-    const ProbBytes b = prob_bytes(p, f_user == nullptr);
+    const ProbBytes b = prob_bytes(p, f_user == nullptr, team);
     memset(D, 0, sizeof(*D));
     D->n = p->n;
     D->d = p->d;
@@ -155,11 +174,14 @@ int prepare(const svm_problem_t* p, const svm_params_t* q, double* alpha, double
     D->list_w = reinterpret_cast<int32_t*>(ws + b.lw);
     D->list_z = reinterpret_cast<int32_t*>(ws + b.lz);
     D->coef = reinterpret_cast<double*>(ws + b.coef);
+    D->team = team;
+    D->trec = reinterpret_cast<unsigned long long*>(ws + b.trec);
     D->res = res;
-    return SVM_OK;
+    e = hipMemsetAsync(D->trec, 0, sizeof(unsigned long long) * 2 * 16 * team, s);
+    return e == hipSuccess ? SVM_OK : SVM_EHIP;
 }
 
-void fill_result(const BatchResult& r, svm_result_t* out) {
+void fill_result(const BatchResult& r, int team, svm_result_t* out) {
     memset(out, 0, sizeof(*out));
     out->beta = r.beta;
     out->b_up = r.b_up;
@@ -173,7 +195,7 @@ void fill_result(const BatchResult& r, svm_result_t* out) {
     out->shrink_passes = r.shrink_passes;
     out->shrunk_total = r.shrunk_total;
     out->n_launches = 1;
-    out->grid_blocks = 1;
+    out->grid_blocks = team;
     out->ms_step = (double)(r.t_end - r.t_start) * 1e-5;   // 100 MHz device wall clock
     out->ms_total = out->ms_step;
 }
@@ -220,7 +242,8 @@ struct Arena {
     }
 };
 
-constexpr int RING = 4096;
+constexpr int RING = 4096;          // descriptor slots
+constexpr int TRING = RING * 16;    // worker tickets
 
 struct Pending {
     int64_t ticket;
@@ -237,16 +260,21 @@ struct Server {
     unsigned char* arena_mem = nullptr;
     Arena arena;
     BatchDesc* ring = nullptr;        // pinned
+    int2* tickets = nullptr;          // pinned
     BatchResult* results = nullptr;   // pinned
     int32_t* tail = nullptr;          // pinned
     int32_t* shutdown = nullptr;      // pinned
-    int32_t* head = nullptr;          // device
+    int32_t* head = nullptr;          // device: [0] next ticket, [16..17] tail / shutdown mirrors
     Ctl* vctl = nullptr;              // device scratch for validation
-    int32_t published = 0;
+    int32_t published = 0;            // descriptors
+    int32_t published_tickets = 0;    // worker tickets
     bool kernel_live = false;
+    bool stop_monitor = false;
+    double last_busy_ms = 0.0;
+    std::thread monitor;
     std::mutex mu;
     struct Live {
-        int32_t slot;
+        int32_t slot, team;
         size_t off, bytes;
     };
     std::map<int64_t, Live> live;     // ticket -> resources (published, not yet observed done)
@@ -263,7 +291,7 @@ struct Server {
             BatchResult& r = results[it->second.slot];
             if (__atomic_load_n(&r.done, __ATOMIC_ACQUIRE)) {
                 svm_result_t out;
-                fill_result(r, &out);
+                fill_result(r, it->second.team, &out);
                 done[it->first] = out;
                 arena.release(it->second.off, it->second.bytes);
                 ++n_completed;
@@ -274,40 +302,53 @@ struct Server {
         }
     }
 
-    // The loop ends by itself after 2 s without work.  If it has ended, every ticket it claimed is
-    // done, and the published tickets still live were never claimed: they are the last |live|
-    // ones, so a new launch starts its tickets there.
+    // The loop is stopped only by the host (park or destroy), and only when no published ticket
+    // is waiting, so a new launch starts its tickets at the published count.
     void ensure_running() {
-        if (kernel_live && hipStreamQuery(ks) == hipSuccess) kernel_live = false;
         if (kernel_live) return;
-        scan_done();
-        const int32_t first = published - (int32_t)live.size();
-        if (hipMemcpyAsync(head, &first, sizeof(int32_t), hipMemcpyHostToDevice, ks) != hipSuccess) return;
+        // head, then the mirrors of tail and shutdown (64 bytes on)
+        int32_t init[18] = {published_tickets};
+        init[16] = published_tickets;
+        if (hipMemcpyAsync(head, init, sizeof(init), hipMemcpyHostToDevice, ks) != hipSuccess) return;
         BatchArgs a{};
         a.descs = ring;
         a.capacity = RING;
+        a.tickets = tickets;
+        a.tcapacity = TRING;
         a.head = head;
         a.tail = tail;
         a.shutdown = shutdown;
-        a.idle_limit = 200ull * 1000 * 1000;
+        a.mirror = head + 16;
         a.fixed_tail = 0;
         if (launch_batch(a, workgroups, SVM_KERNEL_FP32, ks) == hipSuccess) kernel_live = true;
     }
 
+    // stop the loop once every published problem is done (its workgroups return to the GPU)
+    void park() {
+        if (!kernel_live || !live.empty()) return;
+        __atomic_store_n(shutdown, 1, __ATOMIC_RELEASE);
+        (void)hipStreamSynchronize(ks);
+        __atomic_store_n(shutdown, 0, __ATOMIC_RELEASE);
+        kernel_live = false;
+    }
+
     // publish one admitted problem; returns an error code for rejected problems
     int publish(int64_t ticket, const svm_problem_t* p, const svm_params_t* q, double* alpha, size_t off,
-                size_t bytes) {
+                size_t bytes, int team) {
         const int32_t slot = published & (RING - 1);
         BatchDesc D;
         memset(&results[slot], 0, sizeof(BatchResult));
-        int rc = prepare(p, q, alpha, nullptr, arena_mem + off, &results[slot], vctl, cs, &D);
+        int rc = prepare(p, q, team, alpha, nullptr, arena_mem + off, &results[slot], vctl, cs, &D);
         if (rc) return rc;
         if (hipStreamSynchronize(cs) != hipSuccess) return SVM_EHIP;   // packing done before publishing
         ring[slot] = D;
+        for (int r = 0; r < team; ++r) tickets[(published_tickets + r) & (TRING - 1)] = make_int2(slot, r);
         std::atomic_thread_fence(std::memory_order_release);
         ++published;
-        __atomic_store_n(tail, published, __ATOMIC_RELEASE);
-        live[ticket] = Live{slot, off, bytes};
+        published_tickets += team;
+        __atomic_store_n(tail, published_tickets, __ATOMIC_RELEASE);
+        live[ticket] = Live{slot, team, off, bytes};
+        last_busy_ms = now_ms();
         ticket_slot[ticket] = slot;
         ++n_admitted;
         ensure_running();
@@ -315,11 +356,12 @@ struct Server {
     }
 
     bool try_admit(const Pending& w) {
-        const size_t bytes = prob_bytes(&w.prob, true).total;
+        const int team = team_size(w.prob.n, workgroups, w.params.grid_blocks);
+        const size_t bytes = prob_bytes(&w.prob, true, team).total;
         if ((int)live.size() >= max_slots) return false;
         size_t off = 0;
         if (!arena.alloc(bytes, &off)) return false;
-        const int rc = publish(w.ticket, &w.prob, &w.params, w.alpha, off, bytes);
+        const int rc = publish(w.ticket, &w.prob, &w.params, w.alpha, off, bytes, team);
         if (rc) {
             arena.release(off, bytes);
             failed[w.ticket] = rc;
@@ -330,7 +372,17 @@ struct Server {
     void harvest() {
         scan_done();
         while (!waiting.empty() && try_admit(waiting.front())) waiting.pop_front();
-        if (!live.empty()) ensure_running();
+        if (!live.empty()) last_busy_ms = now_ms();
+    }
+
+    void monitor_loop() {
+        for (;;) {
+            std::this_thread::sleep_for(std::chrono::milliseconds(20));
+            std::lock_guard<std::mutex> lk(mu);
+            if (stop_monitor) return;
+            harvest();
+            if (kernel_live && live.empty() && waiting.empty() && now_ms() - last_busy_ms > 2000.0) park();
+        }
     }
 };
 
@@ -350,11 +402,19 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
         if (!alpha[p] || params[p].kernel_precision != kprec) return SVM_EINVAL;
     }
     // one buffer for every problem's solver state, descriptors and results
+    const int wg = std::max(1, std::min(16 * k, batch_max_workgroups(kprec)));
+    std::vector<int> team(k);
+    int64_t nt = 0;
+    for (int p = 0; p < k; ++p) {
+        team[p] = team_size(probs[p].n, wg, params[p].grid_blocks);
+        nt += team[p];
+    }
     std::vector<size_t> off(k);
-    size_t o = al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) + al(sizeof(Ctl) + 256) + al(64);
+    size_t o = al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) + al(sizeof(Ctl) + 256) + al(64) +
+               al(sizeof(int2) * nt);
     for (int p = 0; p < k; ++p) {
         off[p] = o;
-        o += prob_bytes(&probs[p], !(f && f[p])).total;
+        o += prob_bytes(&probs[p], !(f && f[p]), team[p]).total;
     }
     unsigned char* buf = nullptr;
     if (hipMalloc(&buf, o) != hipSuccess) return SVM_ENOMEM;
@@ -363,10 +423,13 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
     Ctl* vctl = reinterpret_cast<Ctl*>(buf + al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k));
     int32_t* head = reinterpret_cast<int32_t*>(buf + al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) +
                                                al(sizeof(Ctl) + 256));
+    int2* dtk = reinterpret_cast<int2*>(buf + al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) +
+                                        al(sizeof(Ctl) + 256) + al(64));
     std::vector<BatchDesc> hd(k);
     int rc = SVM_OK;
     for (int p = 0; p < k && rc == SVM_OK; ++p)
-        rc = prepare(&probs[p], &params[p], alpha[p], f ? f[p] : nullptr, buf + off[p], dres + p, vctl, s, &hd[p]);
+        rc = prepare(&probs[p], &params[p], team[p], alpha[p], f ? f[p] : nullptr, buf + off[p], dres + p, vctl, s,
+                     &hd[p]);
     if (rc) {
         (void)hipStreamSynchronize(s);
         (void)hipFree(buf);
@@ -381,23 +444,30 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
     std::vector<BatchDesc> sorted(k);
-    for (int t = 0; t < k; ++t) sorted[t] = hd[order[t]];
-    // a fixed batch: tickets run 0..k-1, so a mask wider than any ticket indexes the array directly
+    std::vector<int2> tk;
+    tk.reserve(nt);
+    for (int t = 0; t < k; ++t) {
+        sorted[t] = hd[order[t]];
+        for (int r = 0; r < sorted[t].team; ++r) tk.push_back(make_int2(t, r));
+    }
+    // a fixed batch: tickets run 0..nt-1, so a mask wider than any ticket indexes the arrays directly
     const int cap = 1 << 30;
     BatchDesc* dring = ddesc;
     hipError_t e = hipMemcpyAsync(dring, sorted.data(), sizeof(BatchDesc) * k, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dtk, tk.data(), sizeof(int2) * nt, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(dres, 0, sizeof(BatchResult) * k, s);
     if (e == hipSuccess) e = hipMemsetAsync(head, 0, sizeof(int32_t), s);
     BatchArgs a{};
     a.descs = dring;
     a.capacity = cap;
+    a.tickets = dtk;
+    a.tcapacity = cap;
     a.head = head;
     a.tail = head;
     a.shutdown = head;
-    a.idle_limit = 1;
-    a.fixed_tail = k;
-    const int wg = std::max(1, std::min(k, batch_max_workgroups(kprec)));
-    if (e == hipSuccess) e = launch_batch(a, wg, kprec, s);
+    a.mirror = head;
+    a.fixed_tail = (int32_t)nt;
+    if (e == hipSuccess) e = launch_batch(a, (int)std::min<int64_t>(wg, nt), kprec, s);
     std::vector<BatchResult> hr(k);
     if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), dres, sizeof(BatchResult) * k, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -405,7 +475,7 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
     if (e != hipSuccess) return SVM_EHIP;
     int worst = SVM_OK;
     for (int p = 0; p < k; ++p) {
-        fill_result(hr[p], &out[p]);
+        fill_result(hr[p], team[p], &out[p]);
         if (hr[p].status != SVM_OK) worst = hr[p].status;
     }
     return worst;
@@ -416,15 +486,19 @@ int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server) {
     Server* S = new Server();
     S->budget = hbm_budget;
     S->max_slots = max_slots;
-    S->workgroups = std::max(1, std::min(max_slots, batch_max_workgroups(SVM_KERNEL_FP32)));
+    // the loop leaves 8 compute units free: admission validates and packs each problem with small
+    // kernels on another stream while the loop runs
+    const int cus = device_cu_count(), per_cu = cus > 0 ? batch_max_workgroups(SVM_KERNEL_FP32) / cus : 0;
+    S->workgroups = std::max(1, per_cu * std::max(1, cus - 8));
     bool ok = hipStreamCreateWithFlags(&S->ks, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking) == hipSuccess &&
               hipMalloc(&S->arena_mem, hbm_budget) == hipSuccess &&
               hipHostMalloc((void**)&S->ring, sizeof(BatchDesc) * RING, hipHostMallocCoherent) == hipSuccess &&
+              hipHostMalloc((void**)&S->tickets, sizeof(int2) * TRING, hipHostMallocCoherent) == hipSuccess &&
               hipHostMalloc((void**)&S->results, sizeof(BatchResult) * RING, hipHostMallocCoherent) == hipSuccess &&
               hipHostMalloc((void**)&S->tail, 64, hipHostMallocCoherent) == hipSuccess &&
               hipHostMalloc((void**)&S->shutdown, 64, hipHostMallocCoherent) == hipSuccess &&
-              hipMalloc(&S->head, 64) == hipSuccess && hipMalloc(&S->vctl, sizeof(Ctl) + 256) == hipSuccess;
+              hipMalloc(&S->head, 256) == hipSuccess && hipMalloc(&S->vctl, sizeof(Ctl) + 256) == hipSuccess;
     if (!ok) {
         svm_server_destroy(S);
         return SVM_ENOMEM;
@@ -438,6 +512,8 @@ int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server) {
         svm_server_destroy(S);
         return SVM_EHIP;
     }
+    S->last_busy_ms = now_ms();
+    S->monitor = std::thread([S] { S->monitor_loop(); });
     *server = S;
     return SVM_OK;
 }
@@ -449,11 +525,12 @@ int svm_server_submit(void* server, const svm_problem_t* prob, const svm_params_
     int rc = check_batch_problem(prob, params);
     if (rc) return rc;
     if (params->kernel_precision != SVM_KERNEL_FP32) return SVM_EINVAL;
-    if (prob_bytes(prob, true).total > S->budget) return SVM_ENOMEM;
+    if (prob_bytes(prob, true, team_size(prob->n, S->workgroups, params->grid_blocks)).total > S->budget) return SVM_ENOMEM;
     std::lock_guard<std::mutex> lk(S->mu);
     Pending w{S->next_ticket++, *prob, *params, alpha};
     *ticket = w.ticket;
     S->harvest();
+    S->ensure_running();
     if (!S->waiting.empty() || !S->try_admit(w)) {
         S->waiting.push_back(w);
         ++S->n_deferred;
@@ -502,6 +579,13 @@ int svm_server_stats(void* server, int64_t* admitted, int64_t* deferred, int64_t
 int svm_server_destroy(void* server) {
     Server* S = (Server*)server;
     if (!S) return SVM_EINVAL;
+    if (S->monitor.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop_monitor = true;
+        }
+        S->monitor.join();
+    }
     if (S->shutdown) __atomic_store_n(S->shutdown, 1, __ATOMIC_RELEASE);
     if (S->ks) (void)hipStreamSynchronize(S->ks);
     if (S->cs) (void)hipStreamSynchronize(S->cs);
@@ -509,6 +593,7 @@ int svm_server_destroy(void* server) {
     if (S->head) (void)hipFree(S->head);
     if (S->vctl) (void)hipFree(S->vctl);
     if (S->ring) (void)hipHostFree(S->ring);
+    if (S->tickets) (void)hipHostFree(S->tickets);
     if (S->results) (void)hipHostFree(S->results);
     if (S->tail) (void)hipHostFree(S->tail);
     if (S->shutdown) (void)hipHostFree(S->shutdown);

@@ -68,7 +68,7 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
         tickets = {}
         nxt = 0
         t0 = time.perf_counter()
-        last_log = 0
+        last_log, last_t = 0, 0.0
         while nxt < num or tickets:
             now = time.perf_counter() - t0
             while nxt < num and arrivals[nxt] <= now:
@@ -81,9 +81,9 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
                     done_at[j] = time.perf_counter() - t0
                     res_s[j] = got
             done = sum(x is not None for x in done_at)
-            if done - last_log >= 32:
-                last_log = done
-                log("serving: server %d/%d done at %.1f s" % (done, num, time.perf_counter() - t0))
+            if done - last_log >= 32 or time.perf_counter() - t0 > last_t + 20.0:
+                last_log, last_t = done, time.perf_counter() - t0
+                log("serving: server %d/%d done at %.1f s" % (done, num, last_t))
             time.sleep(0.0002)
         span_s = max(done_at)
         stats = srv.stats()

@@ -1,6 +1,8 @@
-"""GPU tests of the batched solver (svm_train_batch) and the serving loop (svm_server_*):
-one workgroup per problem, so each result must be bit-identical alone and in a mix; with FP64
-kernel values each problem follows the FP64 oracle's trajectory."""
+"""GPU tests of the batched solver (svm_train_batch) and the serving loop (svm_server_*).
+
+A team of workgroups solves each problem; selection merges are exact and every row's f update
+is its own, so alpha and f must be bit-identical alone, in a mix and for any team size; with
+FP64 kernel values each problem follows the FP64 oracle's trajectory."""
 import time
 
 import numpy as np
@@ -42,10 +44,10 @@ def mixed_problems(k=6, seed=0):
     return out
 
 
-def run_batch(S, cfgs, prec):
+def run_batch(S, cfgs, prec, team=0):
     import torch
     probs = [S.to_device(c.data) for c in cfgs]
-    params = [S.params_for(c, kernel_precision=prec) for c in cfgs]
+    params = [S.params_for(c, kernel_precision=prec, grid_blocks=team) for c in cfgs]
     alphas = [torch.zeros(c.data.n, dtype=torch.float64, device="cuda") for c in cfgs]
     fs = [torch.zeros(c.data.n, dtype=torch.float64, device="cuda") for c in cfgs]
     rc, res = S.svm_train_batch(probs, params, alphas, fs)
@@ -67,6 +69,53 @@ def test_batch_fp64_follows_oracle(S):
         D = O.dual(c.data, a, c.gamma)
         assert abs(D - O.dual(c.data, ref.alpha, c.gamma)) <= 1e-6 * abs(D)
         assert abs(r.beta - ref.beta) <= 1e-4
+
+
+def team_problems():
+    """Problems large enough for automatic teams of 2-3 workgroups (one of each kind), with
+    shrink passes on every one (earliest schedule).  Their oracle trajectories do not change when
+    every kernel value moves by one ulp, so the device exp (not correctly rounded in every case,
+    unlike the host's) cannot flip a near-tie in the selection; an arbitrary problem can diverge
+    that way after a few hundred iterations and still meets the dual tolerance."""
+    out = []
+    for j, (seed, n, kind) in enumerate([(10, 6500, 0), (1, 6100, 1), (2, 3500, 2)]):
+        r = np.random.default_rng([1406, 5161, 78, seed])
+        data = (g.gen_blobs(n, 20, r) if kind == 0 else g.gen_blobs(n, 128, r) if kind == 1
+                else g.gen_sparse_binary(n, 300, 0.12, r))
+        out.append(g.SvmConfig("team%d" % j, data, C=[1.0, 10.0, 1.0][j], gamma=[0.05, 0.01, 1 / 300][j], eps=1e-3,
+                               shrink_mode=g.SHRINK_MULTI, shrink_kind=g.EARLIEST[0], shrink_param=g.EARLIEST[1]))
+    return out
+
+
+def test_batch_teams_fp64_follow_oracle(S):
+    cfgs = team_problems()
+    rc, res, alphas, fs = run_batch(S, cfgs, S.SVM_KERNEL_FP64)
+    assert rc == S.SVM_OK, S.strerror(rc)
+    for c, r, a, f in zip(cfgs, res, alphas, fs):
+        ref = O.train_config(c)
+        print(c.name, c.data.n, "team", r.grid_blocks, "iters", r.iterations, ref.iterations, flush=True)
+        assert r.grid_blocks == (c.data.n + 2999) // 3000
+        assert r.iterations == ref.iterations and r.n_recon == ref.n_recon
+        assert r.shrink_passes == ref.shrink_passes and r.shrunk_total == ref.shrunk_total
+        assert ref.shrink_passes > 0
+        np.testing.assert_allclose(a, ref.alpha, atol=1e-9)
+        np.testing.assert_allclose(f, ref.f, atol=1e-9)
+        assert abs(r.dual_obj - ref.dual_obj) <= 1e-6 * abs(ref.dual_obj)
+        assert abs(r.beta - ref.beta) <= 1e-4
+
+
+def test_batch_alpha_f_do_not_depend_on_team_size(S):
+    cfgs = team_problems()
+    base = run_batch(S, cfgs, S.SVM_KERNEL_FP32, team=1)
+    assert base[0] == S.SVM_OK
+    for team in (2, 5, 16):
+        rc, res, alphas, fs = run_batch(S, cfgs, S.SVM_KERNEL_FP32, team=team)
+        assert rc == S.SVM_OK
+        for j in range(len(cfgs)):
+            assert res[j].grid_blocks == team
+            assert res[j].iterations == base[1][j].iterations
+            assert np.array_equal(alphas[j], base[2][j]) and np.array_equal(fs[j], base[3][j])
+            assert abs(res[j].dual_obj - base[1][j].dual_obj) <= 1e-9 * abs(base[1][j].dual_obj)
 
 
 def test_batch_result_is_identical_alone_and_in_the_mix(S):
