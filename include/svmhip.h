@@ -203,7 +203,12 @@ int svm_debug_set_trace(int64_t cap, int32_t* i_up, int32_t* i_low, double* b_up
  * wall-clock ticks (100 MHz) it spent in [0] pair staging and update, [1] the
  * f-update / selection / shrink pass, [2] its block reduction, [3] the grid
  * barrier wait, [4] the record merge, [5] the iteration count, [6] staging of
- * the segment at launch, [7] the write-back at exit.  NULL switches it off. */
+ * the segment at launch, [7] the write-back at exit.  Problems admitted to
+ * svm_train_batch (or a server) from this thread while it is set add rank 0's
+ * ticks instead: [0] pair staging and K(up, low), [1] the f-update / selection
+ * / shrink pass, [2] block reduction, [3] team selection exchange, [4]
+ * reconstruction and recompute, [5] iterations, [6] start-up to the first
+ * selection, [7] summary and completion.  NULL switches it off. */
 int svm_debug_set_profile(uint64_t* slots);
 
 /* Residency mode (0 HBM, 1 per-row state in LDS, 2 state and rows in LDS),

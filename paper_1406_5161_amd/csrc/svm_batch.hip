@@ -42,6 +42,7 @@ struct BatchShared {
     long long tcnt;
     int tok;
     double tsum[6];
+    unsigned long long pt[9];   // per-phase timer of rank 0 (slots as in svm_debug_set_profile's batch use)
 };
 
 // Descriptor fields made wave-uniform (scalar registers) after the LDS broadcast.
@@ -583,6 +584,21 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
     const unsigned long long t_start = wall_clock64();
     unsigned seq = 1;
     bool alive = true;
+    // rank 0's per-phase timer: [0] pair staging and K(up, low), [1] f update / selection / shrink
+    // stream, [2] block reduction, [3] team selection exchange, [4] reconstruction and recompute,
+    // [5] iterations, [6] start-up to the first selection, [7] summary and completion
+    const bool prof_on = P.prof != nullptr && rank == 0 && tid == 0;
+    if (prof_on) {
+        for (int k = 0; k < 8; ++k) sh.pt[k] = 0;
+        sh.pt[8] = t_start;
+    }
+    auto lap = [&](int k) {
+        if (prof_on) {
+            const unsigned long long t = wall_clock64();
+            sh.pt[k] += t - sh.pt[8];
+            sh.pt[8] = t;
+        }
+    };
 
     // initial state of this member's rows: alpha = 0, f = -y, active (status bit 3 = shrunk)
     for (int i = seg0 + tid; i < seg1; i += BB) {
@@ -621,6 +637,7 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
         select_block(P, act, nact, sh, cbu, ciu, cbl, cil);
         merge(cbu, ciu, cbl, cil, nact, -1, 0.0, -1, 0.0);
     }
+    lap(6);
     bool shrinking = P.shrink_mode != SVM_SHRINK_NONE;
     double thr = shrinking ? 20.0 * P.eps : 2.0 * P.eps;
     const long long H = shrinking ? P.H : 0;
@@ -726,6 +743,7 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
                 }
             }
             __syncthreads();
+            lap(0);
             const PairNew pn = pair_update(au, al, yu, yl, bu, bl, sh.pair[0], C);
             const KT gam = (KT)P.gamma;
             const KT nuu = dense ? (KT)0 : (KT)sh.pair[1], nll = dense ? (KT)0 : (KT)sh.pair[2];
@@ -791,10 +809,14 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
                     }
                 }
             }
+            lap(1);
             block_reduce_sel_all<BB>(cbu, ciu, cbl, cil, sh.v, sh.i);
             __syncthreads();
+            lap(2);
             if (do_shrink) nact = newcount;
             const long long tot = merge(cbu, ciu, cbl, cil, nact, iu, pn.au, il, pn.al);
+            lap(3);
+            if (prof_on) sh.pt[5] += 1;
             if (do_shrink) {
                 shrunk += nact_total - tot;
                 nact_total = tot;
@@ -807,6 +829,7 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
         if (!alive || status != SVM_OK) break;
         if (shrinking) {
             rebuild(false);                     // the active set meets the tolerance: Alg. 6
+            lap(4);
             ++n_recon;
             if (!alive) break;
             if (bl - bu > 2.0 * P.eps) {
@@ -819,6 +842,7 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
         if (final_recompute && rechecks < 2) {
             ++rechecks;
             rebuild(true);
+            lap(4);
             if (!alive) break;
             if (bl - bu > 2.0 * P.eps) {
                 thr = 2.0 * P.eps;
@@ -832,6 +856,7 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
         rebuild(false);
         ++n_recon;
     }
+    lap(4);
     // ---- threshold and summary over the team
     double x6[6] = {0, 0, 0, 0, 0, 0}, s6[6];
     if (alive) {
@@ -877,6 +902,10 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
             __syncthreads();
             if (!sh.tok) alive = false;
         }
+    }
+    if (prof_on) {
+        lap(7);
+        for (int k = 0; k < 8; ++k) atomicAdd(P.prof + k, sh.pt[k]);
     }
     if (rank == 0 && tid == 0) {
         BatchResult* R = P.res;

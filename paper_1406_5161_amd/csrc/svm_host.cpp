@@ -528,6 +528,8 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
 
 }  // namespace
 
+unsigned long long* svm::debug_profile_slots() { return prof_cfg(); }
+
 extern "C" {
 
 size_t svm_train_workspace_size(const svm_problem_t* prob, const svm_params_t* params) {

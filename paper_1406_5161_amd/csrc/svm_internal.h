@@ -201,6 +201,7 @@ struct BatchDesc {
     int32_t team;                        // workgroups solving this problem together
     int32_t pad2;
     unsigned long long* trec;            // team exchange records [2][team][16], zeroed before the start
+    unsigned long long* prof;            // NULL, or 8 device counters rank 0 adds its phase ticks to
     // per-problem device workspace
     double* alpha;
     double* f;
@@ -226,6 +227,7 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch(const BatchArgs& a, int workgroups, int kprec, hipStream_t s);
+unsigned long long* debug_profile_slots();   // per-phase timer slots set by svm_debug_set_profile
 int batch_max_workgroups(int kprec);
 
 }  // namespace svm

@@ -176,6 +176,7 @@ int prepare(const svm_problem_t* p, const svm_params_t* q, int team, double* alp
     D->coef = reinterpret_cast<double*>(ws + b.coef);
     D->team = team;
     D->trec = reinterpret_cast<unsigned long long*>(ws + b.trec);
+    D->prof = debug_profile_slots();
     D->res = res;
     e = hipMemsetAsync(D->trec, 0, sizeof(unsigned long long) * 2 * 16 * team, s);
     return e == hipSuccess ? SVM_OK : SVM_EHIP;

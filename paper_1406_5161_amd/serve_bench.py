@@ -29,7 +29,9 @@ def _pct(v, q):
 
 
 def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budget_gb: float = 64.0,
-        workers: int = 16) -> dict:
+        workers: int = 16, detail: list | None = None) -> dict:
+    """Runs both paths on the same trace; with `detail` (a list) appends one record per problem:
+    shape, team size, iterations and device / host times of both paths."""
     import torch
     from . import svmhip as S
     t_gen = time.perf_counter()
@@ -43,7 +45,7 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
     # ---- plain loop: one problem at a time, FIFO, each waits for its arrival
     alphas_p = [torch.zeros(c.data.n, dtype=torch.float64, device="cuda") for c in cfgs]
     ws = None
-    lat_p, duals_p, its_p = [], [], 0
+    lat_p, duals_p, its_p, ms_p = [], [], 0, []
     t0 = time.perf_counter()
     for j, c in enumerate(cfgs):
         now = time.perf_counter() - t0
@@ -54,6 +56,7 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
         lat_p.append(time.perf_counter() - t0 - arrivals[j])
         duals_p.append(r.dual_obj)
         its_p += r.iterations
+        ms_p.append((r.ms_total, r.iterations, r.grid_blocks))
         if (j + 1) % 32 == 0:
             log("serving: plain loop %d/%d done at %.1f s" % (j + 1, num, time.perf_counter() - t0))
     span_p = time.perf_counter() - t0
@@ -91,6 +94,13 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
     lat_s = [done_at[j] - arrivals[j] for j in range(num)]
     rel = [abs(res_s[j][1].dual_obj - duals_p[j]) / max(1e-300, abs(duals_p[j])) for j in range(num)]
     its_s = sum(res_s[j][1].iterations for j in range(num))
+    if detail is not None:
+        for j, c in enumerate(cfgs):
+            r = res_s[j][1]
+            detail.append({"j": j, "n": c.data.n, "d": c.data.d, "layout": c.data.layout, "C": c.C,
+                           "gamma": c.gamma, "arrival": float(arrivals[j]), "done": done_at[j],
+                           "team": r.grid_blocks, "iters": r.iterations, "ms_device": r.ms_step,
+                           "plain_ms": ms_p[j][0], "plain_iters": ms_p[j][1], "plain_grid": ms_p[j][2]})
     out = {
         "problems": num, "rate_hz": rate_hz,
         "plain": {"solves_per_s": num / span_p, "makespan_s": span_p, "p50_latency_s": _pct(lat_p, 50),
