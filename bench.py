@@ -56,12 +56,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
+def traffic_from_profile(workload):
+    """HBM bytes per loop launch from the committed counter summary, if it was taken on this
+    workload and the loop kernel's sources have not changed since."""
     try:
         prof = json.load(open(PROFILE_COUNTERS))
     except Exception:
         return None
-    if prof.get("kernel_source_sha256_16") != kernel_source_hash():
+    if prof.get("kernel_source_sha256_16") != kernel_source_hash() or prof.get("workload") != workload:
         return None
     return prof.get("hbm_bytes_per_launch")
 
@@ -147,7 +149,7 @@ def main():
     byts = sum(algorithmic_bytes(r, data) for r in results)
     achieved = byts / (loop_ms * 1e-3) / 1e9
     per_launch_bytes = byts / max(1, launches)
-    traffic = traffic_from_profile()
+    traffic = traffic_from_profile(cfg.name)
 
     last = results[-1]
     out = {

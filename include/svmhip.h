@@ -145,8 +145,11 @@ int svm_decision(const svm_problem_t* train, const double* alpha, double beta, d
                  const svm_problem_t* queries, double* out, int32_t kernel_precision, void* stream);
 
 /* Several independent problems in one persistent fused launch: problem p is
- * solved by its own team of workgroups (one to 16, about 3000 samples per
- * workgroup unless params[p].grid_blocks sets it), problems never synchronise
+ * solved by its own team of workgroups (one to 64: the smallest team whose
+ * members can each keep their share of the samples, with its rows, in LDS,
+ * when that share is at least 512 samples; else about 3000 samples per
+ * workgroup, at most 16; params[p].grid_blocks overrides), problems never
+ * synchronise
  * with each other.  Every problem runs the whole method of svm_train (SMO
  * loop, shrinking, reconstruction, closing recompute) inside its team; alpha
  * and f do not depend on the team size or on the other problems.  alpha[p]
@@ -161,15 +164,20 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
 
 /* ---- serving: continuous batching of training problems */
 /* Create a server with a device-memory budget (bytes of solver state it may
- * keep resident) and at most max_slots problems in flight.  The server owns
- * one persistent device loop whose workgroups pick up admitted problems (a
- * team per problem, as in svm_train_batch) as slots and memory free up; a
- * host thread admits waiting problems as running ones complete and stops the
- * loop after 2 s without work (the next submit starts it again).  FP32
- * kernel values only. */
+ * keep resident) and at most max_slots (1..1024) problems in flight.  The
+ * server owns one persistent device loop whose workgroups validate and pack
+ * each admitted problem, then solve it (a team per problem, as in
+ * svm_train_batch) as slots and memory free up; a host thread admits waiting
+ * problems as running ones complete and stops the loop after 2 s without
+ * work (the next submit starts it again).  While the loop runs it holds all
+ * but 8 compute units, so other device work of the process (copies,
+ * kernels) runs on those 8.  FP32 kernel values only. */
 int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server);
 /* Queue a problem (its arrays must stay valid until the ticket completes).
- * alpha: n doubles (device) that receive the solution.  Returns a ticket. */
+ * alpha: n doubles (device) that receive the solution.  Returns a ticket; a
+ * problem that fails the loop's validation (SVM_EINVAL, SVM_ENONFINITE,
+ * SVM_EONECLASS, SVM_EUNSUPPORTED) or needs more solver state than the whole
+ * budget (SVM_ENOMEM) gets a ticket whose svm_server_poll returns that error. */
 int svm_server_submit(void* server, const svm_problem_t* prob, const svm_params_t* params, double* alpha,
                       int64_t* ticket);
 /* SVM_OK and *out filled when done, SVM_EBUSY while queued or running. */

@@ -22,8 +22,8 @@ namespace svm {
 
 constexpr int BB = BATCH_BLOCK;
 constexpr int BNW = BB / 64;
-constexpr int SUMR = 8;                   // rows of A per tile in block-local kernel sums
-constexpr size_t BATCH_LDS = 120 * 1024;  // dynamic LDS of the batched loop
+constexpr int SUMR = BATCH_SUMR;          // rows per tile in block-local kernel sums
+constexpr size_t BATCH_LDS = BATCH_LDS_BYTES;
 
 struct BatchShared {
     BatchDesc P;
@@ -36,13 +36,13 @@ struct BatchShared {
     long long cnt;
     int ticket;
     int rank;
-    int prev_n;
     double tsel[4];
     int tseli[2];
     long long tcnt;
     int tok;
     double tsum[6];
     unsigned long long pt[9];   // per-phase timer of rank 0 (slots as in svm_debug_set_profile's batch use)
+    int pr[5];                  // preparation job: err, n_pos, n_neg, max_row_nnz, not-pattern
 };
 
 // Descriptor fields made wave-uniform (scalar registers) after the LDS broadcast.
@@ -54,6 +54,7 @@ DEV T* uptr(T* p) {
     return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
 }
 DEV int ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
+DEV size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
 DEV long long ull_(long long v) {
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffll));
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
@@ -102,78 +103,25 @@ DEV int block_scan_keep(bool keep, int* s_wc, int& total) {
     return off + wpre;
 }
 
-template <typename KT>
-DEV void row_dist(const BatchDesc& P, const float2* pairv, int i, int gl, int lpr, KT nuu, KT nll, KT& du2,
-                  KT& dl2) {
-    if (P.lay == LAY_DENSE) {
-        const float4* x4 = reinterpret_cast<const float4*>(P.x + (size_t)i * P.dpad);
-        const float4* p4 = reinterpret_cast<const float4*>(pairv);
-        KT a = 0, b = 0;
-        for (int k4 = gl; k4 < P.dpad / 4; k4 += lpr) {
-            const float4 v = x4[k4];
-            const float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
-            if constexpr (std::is_same<KT, double>::value) {
-#pragma clang fp contract(off)
-                double t;
-                t = (double)v.x - (double)q0.x; a = a + t * t;
-                t = (double)v.x - (double)q0.y; b = b + t * t;
-                t = (double)v.y - (double)q0.z; a = a + t * t;
-                t = (double)v.y - (double)q0.w; b = b + t * t;
-                t = (double)v.z - (double)q1.x; a = a + t * t;
-                t = (double)v.z - (double)q1.y; b = b + t * t;
-                t = (double)v.w - (double)q1.z; a = a + t * t;
-                t = (double)v.w - (double)q1.w; b = b + t * t;
-            } else {
-                float t;
-                t = v.x - q0.x; a = fmaf(t, t, a);
-                t = v.x - q0.y; b = fmaf(t, t, b);
-                t = v.y - q0.z; a = fmaf(t, t, a);
-                t = v.y - q0.w; b = fmaf(t, t, b);
-                t = v.z - q1.x; a = fmaf(t, t, a);
-                t = v.z - q1.y; b = fmaf(t, t, b);
-                t = v.w - q1.z; a = fmaf(t, t, a);
-                t = v.w - q1.w; b = fmaf(t, t, b);
-            }
-        }
-        du2 = group_sum(a, lpr);
-        dl2 = group_sum(b, lpr);
-    } else {
-        const int p0 = P.row_ptr[i], p1 = P.row_ptr[i + 1];
-        KT nn = 0, su = 0, sl = 0;
-        for (int p = p0 + gl; p < p1; p += lpr) {
-            const int c = P.col[p];
-            const KT v = P.pattern_only ? (KT)1 : (KT)P.val[p];
-            const float2 ul = pairv[c];
-            nn += v * v;
-            su += v * (KT)ul.x;
-            sl += v * (KT)ul.y;
-        }
-        nn = group_sum(nn, lpr);
-        su = group_sum(su, lpr);
-        sl = group_sum(sl, lpr);
-        du2 = nn + nuu - (KT)2 * su;
-        dl2 = nn + nll - (KT)2 * sl;
-        if (du2 < (KT)0) du2 = (KT)0;
-        if (dl2 < (KT)0) dl2 = (KT)0;
-    }
-}
-
 // Distances of RPT rows at once: the rows' loads are interleaved so a lane keeps several
-// rows in flight instead of walking one dependent chain after another.
-template <typename KT, int RPT>
-DEV void rows_dist(const BatchDesc& P, const float2* pairv, const int* ii, const bool* vv, int gl, int lpr,
-                   KT nuu, KT nll, KT* du2, KT* dl2) {
-    if (P.lay == LAY_DENSE) {
+// rows in flight instead of walking one dependent chain after another.  Row r of the call is
+// ri[r] in the row source: dense rows at xb + ri * dpad; CSR rows [off[ri], off[ri + 1]) of
+// cols / vals.  The source is the problem's arrays in HBM or the member's copy in LDS.
+template <typename KT, int RPT, typename OT, typename CT>
+DEV void rows_dist(bool dense, int dpad, const float* xb, const OT* off, const CT* cols, const float* vals,
+                   bool pattern, const float2* pairv, const int* ri, const bool* vv, int gl, int lpr, KT nuu,
+                   KT nll, KT* du2, KT* dl2) {
+    if (dense) {
         const float4* p4 = reinterpret_cast<const float4*>(pairv);
         KT a[RPT], b[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) { a[r] = 0; b[r] = 0; }
-        for (int k4 = gl; k4 < P.dpad / 4; k4 += lpr) {
+        for (int k4 = gl; k4 < dpad / 4; k4 += lpr) {
             const float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
             float4 v[RPT];
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
-                v[r] = vv[r] ? reinterpret_cast<const float4*>(P.x + (size_t)ii[r] * P.dpad)[k4]
+                v[r] = vv[r] ? reinterpret_cast<const float4*>(xb + (size_t)ri[r] * dpad)[k4]
                              : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -212,8 +160,8 @@ DEV void rows_dist(const BatchDesc& P, const float2* pairv, const int* ii, const
         int p0[RPT], p1[RPT], len = 0;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            p0[r] = vv[r] ? P.row_ptr[ii[r]] : 0;
-            p1[r] = vv[r] ? P.row_ptr[ii[r] + 1] : 0;
+            p0[r] = vv[r] ? (int)off[ri[r]] : 0;
+            p1[r] = vv[r] ? (int)off[ri[r] + 1] : 0;
         }
 #pragma unroll
         for (int r = 0; r < RPT; ++r) len = max(len, p1[r] - p0[r]);
@@ -227,8 +175,8 @@ DEV void rows_dist(const BatchDesc& P, const float2* pairv, const int* ii, const
             for (int r = 0; r < RPT; ++r) {
                 const int p = p0[r] + k;
                 const bool in = p < p1[r];
-                c[r] = in ? P.col[p] : -1;
-                fv[r] = in ? (P.pattern_only ? 1.f : P.val[p]) : 0.f;
+                c[r] = in ? (int)cols[p] : -1;
+                fv[r] = in ? (pattern ? 1.f : vals[p]) : 0.f;
             }
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -576,11 +524,35 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
     int32_t* lw = P.list_w + seg0;
     int32_t* lz = P.list_z + (size_t)rank * n;
     double* lcoef = P.coef + (size_t)rank * n;
+    // dynamic LDS: pair rows (float2 per feature), the reconstruction tile (SUMR rows), then,
+    // when it fits, this member's segment: f, status, active list and its rows
+    const int W = dense ? P.dpad : P.d;
     float2* pairv = reinterpret_cast<float2*>(dyn);
-    const int pair_entries = dense ? P.dpad : P.d;
-    int* prev_cols = reinterpret_cast<int*>(dyn + sizeof(float2) * (size_t)pair_entries);
-    const size_t tile_off = (sizeof(float2) * (size_t)pair_entries + sizeof(int) * 2 * 4096 + 15) & ~(size_t)15;
+    const size_t tile_off = al16(sizeof(float2) * (size_t)W);
     float* tile = reinterpret_cast<float*>(dyn + tile_off);
+    unsigned char* segmem = dyn + tile_off + al16(sizeof(float) * SUMR * (size_t)W);
+    const int m = seg1 - seg0;
+    const int nnz0 = dense ? 0 : P.row_ptr[seg0];
+    const int nnz_seg = dense ? 0 : P.row_ptr[seg1] - nnz0;
+    const bool pat = P.pattern_only != 0;
+    size_t so = al16(sizeof(double) * (size_t)m);
+    double* f_l = reinterpret_cast<double*>(segmem);
+    float* x_l = reinterpret_cast<float*>(segmem + so);
+    uint32_t* off_l = reinterpret_cast<uint32_t*>(segmem + so);
+    if (dense) {
+        so += al16(sizeof(float) * (size_t)m * P.dpad);
+    } else {
+        so += al16(sizeof(uint32_t) * (size_t)(m + 1));
+    }
+    uint16_t* cols_l = reinterpret_cast<uint16_t*>(segmem + so);
+    if (!dense) so += al16(sizeof(uint16_t) * (size_t)nnz_seg);
+    float* vals_l = reinterpret_cast<float*>(segmem + so);
+    if (!dense && !pat) so += al16(sizeof(float) * (size_t)nnz_seg);
+    uint8_t* st_l = segmem + so;
+    so += al16((size_t)m);
+    uint16_t* act_l = reinterpret_cast<uint16_t*>(segmem + so);
+    so += al16(sizeof(uint16_t) * (size_t)m);
+    const bool res = (size_t)(segmem - dyn) + so <= BATCH_LDS && m <= 65535 && (dense || P.d <= 65536);
     const unsigned long long t_start = wall_clock64();
     unsigned seq = 1;
     bool alive = true;
@@ -608,9 +580,6 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
         P.status[i] = st_make(yp, 0.0, C);
         act[i - seg0] = i;
     }
-    if (!dense)
-        for (int k = tid; k < P.d; k += BB) pairv[k] = make_float2(0.f, 0.f);
-    if (tid == 0) sh.prev_n = 0;
     __syncthreads();
 
     int nact = seg1 - seg0;
@@ -637,6 +606,36 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
         select_block(P, act, nact, sh, cbu, ciu, cbl, cil);
         merge(cbu, ciu, cbl, cil, nact, -1, 0.0, -1, 0.0);
     }
+    // f, status and active list between HBM and the LDS copy (resident members only)
+    auto to_global = [&]() {
+        for (int r = tid; r < m; r += BB) {
+            P.f[seg0 + r] = f_l[r];
+            P.status[seg0 + r] = st_l[r];
+        }
+        __syncthreads();
+    };
+    auto from_global = [&]() {
+        for (int r = tid; r < m; r += BB) {
+            f_l[r] = P.f[seg0 + r];
+            st_l[r] = P.status[seg0 + r];
+            act_l[r] = (uint16_t)r;
+        }
+        __syncthreads();
+    };
+    if (res) {
+        if (dense) {
+            const float4* src = reinterpret_cast<const float4*>(P.x + (size_t)seg0 * P.dpad);
+            float4* dst = reinterpret_cast<float4*>(x_l);
+            for (int k = tid; k < m * (P.dpad / 4); k += BB) dst[k] = src[k];
+        } else {
+            for (int r = tid; r <= m; r += BB) off_l[r] = (uint32_t)(P.row_ptr[seg0 + r] - nnz0);
+            for (int k = tid; k < nnz_seg; k += BB) {
+                cols_l[k] = (uint16_t)P.col[nnz0 + k];
+                if (!pat) vals_l[k] = P.val[nnz0 + k];
+            }
+        }
+        from_global();
+    }
     lap(6);
     bool shrinking = P.shrink_mode != SVM_SHRINK_NONE;
     double thr = shrinking ? 20.0 * P.eps : 2.0 * P.eps;
@@ -649,6 +648,7 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
     auto rebuild = [&](bool all) {
         const double zero6[6] = {0, 0, 0, 0, 0, 0};
         double t6[6];
+        if (res) to_global();
         if (!team_sum(P, rank, seq++, zero6, t6, true, sh)) { alive = false; return; }   // publishes alpha
         const int nz = compact_block<1>(P, 0, n, lz, lcoef, sh);
         if (all) {
@@ -668,6 +668,7 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
         int ciu, cil;
         select_block(P, act, nact, sh, cbu, ciu, cbl, cil);
         merge(cbu, ciu, cbl, cil, nact, -1, 0.0, -1, 0.0);
+        if (res) from_global();
     };
 
     while (alive) {
@@ -704,19 +705,11 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
                 const int pu0 = P.row_ptr[iu], pu1 = P.row_ptr[iu + 1];
                 const int pl0 = P.row_ptr[il], pl1 = P.row_ptr[il + 1];
                 const int nu = pu1 - pu0, nl = pl1 - pl0;
-                for (int j = tid; j < sh.prev_n; j += BB) pairv[prev_cols[j]] = make_float2(0.f, 0.f);
+                for (int k = tid; k < P.d; k += BB) pairv[k] = make_float2(0.f, 0.f);
                 __syncthreads();
                 float* pf = reinterpret_cast<float*>(pairv);
-                for (int p = tid; p < nu; p += BB) {
-                    const int c = P.col[pu0 + p];
-                    pf[2 * c] = P.pattern_only ? 1.f : P.val[pu0 + p];
-                    prev_cols[p] = c;
-                }
-                for (int p = tid; p < nl; p += BB) {
-                    const int c = P.col[pl0 + p];
-                    pf[2 * c + 1] = P.pattern_only ? 1.f : P.val[pl0 + p];
-                    prev_cols[nu + p] = c;
-                }
+                for (int p = tid; p < nu; p += BB) pf[2 * P.col[pu0 + p]] = pat ? 1.f : P.val[pu0 + p];
+                for (int p = tid; p < nl; p += BB) pf[2 * P.col[pl0 + p] + 1] = pat ? 1.f : P.val[pl0 + p];
                 __syncthreads();
                 if (wid == 0) {
                     KT su = 0, sl = 0, dot = 0;
@@ -738,7 +731,6 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
                         sh.pair[0] = (double)kexp((KT)(-(KT)P.gamma * d2));
                         sh.pair[1] = (double)su;
                         sh.pair[2] = (double)sl;
-                        sh.prev_n = nu + nl;
                     }
                 }
             }
@@ -757,16 +749,22 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
             int newcount = 0;
             constexpr int RPT = 4;
             for (int base = 0; base < nact; base += NG * RPT) {
-                int ii[RPT];
+                int ii[RPT], rr[RPT];
                 bool vv[RPT];
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     const int t = base + r * NG + g;
                     vv[r] = t < nact;
-                    ii[r] = vv[r] ? act[t] : 0;
+                    rr[r] = vv[r] ? (res ? (int)act_l[t] : act[t] - seg0) : 0;
+                    ii[r] = seg0 + rr[r];
                 }
                 KT du2[RPT], dl2[RPT];
-                rows_dist<KT, RPT>(P, pairv, ii, vv, gl, lpr, nuu, nll, du2, dl2);
+                if (res)
+                    rows_dist<KT, RPT>(dense, P.dpad, x_l, off_l, cols_l, vals_l, pat, pairv, rr, vv, gl, lpr, nuu,
+                                       nll, du2, dl2);
+                else
+                    rows_dist<KT, RPT>(dense, P.dpad, P.x, P.row_ptr, P.col, P.val, pat, pairv, ii, vv, gl, lpr,
+                                       nuu, nll, du2, dl2);
                 bool keep[RPT];
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
@@ -775,24 +773,26 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
                     if (vv[r] && gl == 0) {
                         const double ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2[r]);
                         const double kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2[r]);
+                        double* fp = res ? f_l + rr[r] : P.f + i;
+                        uint8_t* sp = res ? st_l + rr[r] : P.status + i;
                         double fi;
                         {
 #pragma clang fp contract(off)
-                            fi = P.f[i] + (pn.cu * ku + pn.cl * kl);
+                            fi = *fp + (pn.cu * ku + pn.cl * kl);
                         }
-                        P.f[i] = fi;
-                        uint8_t st = P.status[i];
+                        *fp = fi;
+                        uint8_t st = *sp;
                         if (i == iu) {
                             st = st_make(yu > 0, pn.au, C);
-                            P.status[i] = st;
+                            *sp = st;
                             st_agent(P.alpha + i, pn.au);
                         } else if (i == il) {
                             st = st_make(yl > 0, pn.al, C);
-                            P.status[i] = st;
+                            *sp = st;
                             st_agent(P.alpha + i, pn.al);
                         }
                         keep[r] = !(do_shrink && shrink_rule(st, fi, bu, bl));
-                        if (!keep[r]) P.status[i] = st | 8;
+                        if (!keep[r]) *sp = st | 8;
                         if (keep[r]) {
                             if (st_in_up(st) && better_up(fi, i, cbu, ciu)) { cbu = fi; ciu = i; }
                             if (st_in_low(st) && better_low(fi, i, cbl, cil)) { cbl = fi; cil = i; }
@@ -804,7 +804,10 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
                     for (int r = 0; r < RPT; ++r) {
                         int tot;
                         const int pos = block_scan_keep(keep[r], sh.wc, tot);
-                        if (keep[r]) act[newcount + pos] = ii[r];
+                        if (keep[r]) {
+                            if (res) act_l[newcount + pos] = (uint16_t)rr[r];
+                            else act[newcount + pos] = ii[r];
+                        }
                         newcount += tot;
                     }
                 }
@@ -858,6 +861,7 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
     }
     lap(4);
     // ---- threshold and summary over the team
+    if (res) to_global();
     double x6[6] = {0, 0, 0, 0, 0, 0}, s6[6];
     if (alive) {
         double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0;
@@ -929,6 +933,78 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
     __syncthreads();
 }
 
+// Preparation job of the serving loop (one workgroup): the checks of the one-problem entry
+// point's validation (labels +-1, finite values, CSR rows with increasing in-range columns),
+// class counts, the largest CSR row, whether every CSR value is 1.0, dense packing into
+// [n][dpad] rows, and zeroed team records.  The host reads the outcome from pinned memory, so
+// admission never needs a kernel of its own while the loop holds the GPU.
+DEV void prep_job(BatchShared& sh) {
+    const BatchDesc& P = sh.P;
+    const int tid = threadIdx.x;
+    const int n = P.n, d = P.d;
+    if (tid < 5) sh.pr[tid] = 0;
+    __syncthreads();
+    int err = 0, npos = 0, nneg = 0, maxnnz = 0, notpat = 0;
+    for (int i = tid; i < n; i += BB) {
+        const int8_t v = P.y[i];
+        if (v == 1) ++npos;
+        else if (v == -1) ++nneg;
+        else err |= 1;
+    }
+    if (P.src_layout == SVM_CSR) {
+        for (int i = tid; i < n; i += BB) {
+            const int p0 = P.row_ptr[i], p1 = P.row_ptr[i + 1];
+            if (i == 0 && p0 != 0) err |= 1;
+            if (p1 < p0) {
+                err |= 1;
+                continue;
+            }
+            maxnnz = max(maxnnz, p1 - p0);
+            for (int p = p0; p < p1; ++p) {
+                const int c = P.col[p];
+                if (c < 0 || c >= d) err |= 1;
+                if (p > p0 && c <= P.col[p - 1]) err |= 1;
+                const float v = P.val[p];
+                if (!isfinite(v)) err |= 2;
+                if (v != 1.f) notpat = 1;
+            }
+        }
+    } else {
+        const bool fm = P.src_layout == SVM_DENSE_FEATURE_MAJOR;
+        const size_t tot = (size_t)n * P.dpad;
+        float* out = const_cast<float*>(P.x);
+        for (size_t e = tid; e < tot; e += BB) {
+            const int i = (int)(e / P.dpad), k = (int)(e % P.dpad);
+            float v = 0.f;
+            if (k < d) v = fm ? P.xsrc[(size_t)k * P.ldx + i] : P.xsrc[(size_t)i * P.ldx + k];
+            if (!isfinite(v)) err |= 2;
+            out[e] = v;
+        }
+    }
+    for (int k = tid; k < 2 * 16 * TEAM_MAX; k += BB) P.trec[k] = 0ull;
+    if (err) atomicOr(&sh.pr[0], err);
+    if (npos) atomicAdd(&sh.pr[1], npos);
+    if (nneg) atomicAdd(&sh.pr[2], nneg);
+    if (maxnnz) atomicMax(&sh.pr[3], maxnnz);
+    if (notpat) atomicOr(&sh.pr[4], 1);
+    __syncthreads();
+    if (tid == 0) {
+        PrepOut* o = P.prep;
+        __hip_atomic_store(&o->err, sh.pr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&o->n_pos, sh.pr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&o->n_neg, sh.pr[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&o->max_row_nnz, sh.pr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&o->nnz, P.src_layout == SVM_CSR ? P.row_ptr[n] : 0, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&o->pattern, sh.pr[4] ? 0 : 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    // every thread's packed rows and zeroed records are released before the flag
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&P.prep->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __syncthreads();
+}
+
 template <typename KT>
 __global__ __launch_bounds__(BB) void smo_batch_kernel(BatchArgs A) {
     extern __shared__ __align__(16) unsigned char dyn[];
@@ -973,7 +1049,8 @@ __global__ __launch_bounds__(BB) void smo_batch_kernel(BatchArgs A) {
         }
         __syncthreads();
         if (sh.ticket < 0) break;
-        solve_team<KT>(sh, dyn);
+        if (sh.rank < 0) prep_job(sh);
+        else solve_team<KT>(sh, dyn);
     }
 }
 

@@ -174,6 +174,9 @@ namespace svm {
 // ---- batched / serving solver: a team of workgroups solves one problem
 
 constexpr int BATCH_BLOCK = 512;
+constexpr size_t BATCH_LDS_BYTES = 120 * 1024;   // dynamic LDS of a batched workgroup
+constexpr int BATCH_SUMR = 8;                     // rows per reconstruction tile
+constexpr int TEAM_MAX = 64;                      // workgroups per problem (one wave merges them)
 
 struct BatchResult {
     double beta, b_up, b_low, dual_obj;
@@ -181,6 +184,14 @@ struct BatchResult {
     int32_t n_sv, n_bsv, n_recon, status;
     long long shrink_passes, shrunk_total;
     unsigned long long t_start, t_end;   // device wall clock (100 MHz) around the solve
+    int32_t done;                        // set last (release) when the fields above are final
+    int32_t pad;
+};
+
+// Outcome of a preparation job (validation, counts, dense packing) run by the serving loop.
+struct PrepOut {
+    int32_t err;                         // bit 0 malformed input, bit 1 non-finite value
+    int32_t n_pos, n_neg, max_row_nnz, nnz, pattern;
     int32_t done;                        // set last (release) when the fields above are final
     int32_t pad;
 };
@@ -202,6 +213,13 @@ struct BatchDesc {
     int32_t pad2;
     unsigned long long* trec;            // team exchange records [2][team][16], zeroed before the start
     unsigned long long* prof;            // NULL, or 8 device counters rank 0 adds its phase ticks to
+    // preparation jobs only (ticket rank -1): the caller's samples, validated and, for dense
+    // layouts, packed into x; the team records (TEAM_MAX members) are zeroed
+    const float* xsrc;
+    int64_t ldx;
+    int32_t src_layout;                  // SVM_DENSE_ROW_MAJOR | SVM_DENSE_FEATURE_MAJOR | SVM_CSR
+    int32_t pad3;
+    PrepOut* prep;                       // pinned host memory
     // per-problem device workspace
     double* alpha;
     double* f;
@@ -217,7 +235,7 @@ struct BatchArgs {
     const BatchDesc* descs;              // descriptor ring (device or pinned host)
     int32_t capacity;                    // ring size (power of two)
     int32_t tcapacity;                   // ticket ring size (power of two)
-    const int2* tickets;                 // worker ticket -> (descriptor slot, rank in the team)
+    const int2* tickets;                 // worker ticket -> (descriptor slot, rank in the team; -1: preparation)
     int32_t* head;                       // device counter: next ticket
     const int32_t* tail;                 // number of published tickets (host-written when serving)
     const int32_t* shutdown;             // host sets 1 to stop the loop; set only when no ticket waits

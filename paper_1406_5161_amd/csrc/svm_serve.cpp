@@ -2,7 +2,8 @@
 // (svm_server_*): continuous batching of SVM training problems on one GPU.
 //
 // Both run the persistent batched kernel of svm_batch.hip, in which a team of
-// one to 16 workgroups solves one problem (the team size grows with n).  Each
+// one to TEAM_MAX workgroups solves one problem (sized so each member's share
+// of the samples fits its LDS when that is possible).  Each
 // workgroup takes worker tickets; ticket t names a descriptor slot and a rank
 // in that problem's team, and the tickets of one problem are consecutive.  The
 // batch entry point hands the kernel a fixed ticket table; the server keeps the
@@ -39,6 +40,7 @@ namespace {
 constexpr size_t SALIGN = 256;
 size_t al(size_t v) { return (v + SALIGN - 1) & ~(SALIGN - 1); }
 int dpad4(int d) { return (d + 3) & ~3; }
+double al16(double v) { return std::ceil(v / 16.0) * 16.0; }
 
 // ---- shape autotuning: lanes per row of the batched loop.
 // Rules measured on gfx950 for one workgroup per problem: enough lanes that a
@@ -58,11 +60,15 @@ int tune_lanes_per_row(const svm_problem_t* p, double avg_nnz, int kprec, int re
     return l;
 }
 
+// Solver state of one problem: a base part that does not depend on the team size (packed
+// dense rows, f, status, active and work lists, team records for `rec_members` members) and a
+// team part (each member's support-vector list and coefficients).
 struct ProbBytes {
-    size_t x, f, status, act, lw, lz, coef, trec, total;
+    size_t x, f, status, act, lw, trec, base;   // offsets into the base part, its size
+    size_t lz, coef, team;                      // offsets into the team part, its size
 };
 
-ProbBytes prob_bytes(const svm_problem_t* p, bool need_f, int team) {
+ProbBytes prob_bytes(const svm_problem_t* p, bool need_f, int team, int rec_members) {
     ProbBytes b{};
     const size_t n = (size_t)p->n;
     size_t o = 0;
@@ -72,10 +78,12 @@ ProbBytes prob_bytes(const svm_problem_t* p, bool need_f, int team) {
     b.status = take(n);
     b.act = take(sizeof(int32_t) * n);
     b.lw = take(sizeof(int32_t) * n);
+    b.trec = take(sizeof(unsigned long long) * 2 * 16 * rec_members);
+    b.base = o;
+    o = 0;
     b.lz = take(sizeof(int32_t) * n * team);
     b.coef = take(sizeof(double) * n * team);
-    b.trec = take(sizeof(unsigned long long) * 2 * 16 * team);
-    b.total = o;
+    b.team = o;
     return b;
 }
 
@@ -87,26 +95,49 @@ int check_batch_problem(const svm_problem_t* p, const svm_params_t* q) {
     if (q->kernel_precision != SVM_KERNEL_FP32 && q->kernel_precision != SVM_KERNEL_FP64) return SVM_EINVAL;
     int l = q->lanes_per_row;
     if (l < 0 || l > 64 || (l & (l - 1))) return SVM_EINVAL;
+    // LDS of a batched workgroup: pair rows (8 B per feature) and the reconstruction tile
+    // (BATCH_SUMR densified rows, 4 B per feature)
+    const int W = p->layout == SVM_CSR ? p->d : dpad4(p->d);
+    if (al16(8.0 * W) + al16(4.0 * BATCH_SUMR * W) + 1024.0 > (double)BATCH_LDS_BYTES) return SVM_EUNSUPPORTED;
     if (p->layout == SVM_CSR) {
         if (!p->row_ptr || !p->col || !p->val) return SVM_EINVAL;
-        // LDS of the batched loop: pair table (d) + tile of 16 densified rows (16 d)
-        if (8.0 * p->d + 32768.0 + 64.0 * p->d > 118.0 * 1024) return SVM_EUNSUPPORTED;
     } else {
         if (!p->x) return SVM_EINVAL;
         if (p->layout == SVM_DENSE_ROW_MAJOR && p->ldx < p->d) return SVM_EINVAL;
         if (p->layout == SVM_DENSE_FEATURE_MAJOR && p->ldx < p->n) return SVM_EINVAL;
-        if (8.0 * dpad4(p->d) + 32768.0 + 64.0 * dpad4(p->d) > 118.0 * 1024) return SVM_EUNSUPPORTED;
     }
     return SVM_OK;
 }
 
-// Team size: the requested one (params.grid_blocks), else about 3000 rows per workgroup; at most
-// 16 and at most the workgroups of the launch.
-int team_size(int n, int workers, int requested) {
-    int b = requested > 0 ? requested : (n + 2999) / 3000;
-    if (b > 16) b = 16;
-    if (b > workers) b = workers;
-    return b < 1 ? 1 : b;
+// What admission learns about a problem before it allocates anything for it.
+struct Inspect {
+    int32_t nnz = 0;          // CSR nonzeros
+    int32_t pattern = 0;      // CSR values all 1.0
+};
+
+// Team size.  The requested one (params.grid_blocks) if set.  Otherwise the smallest team
+// whose members can each hold their segment (f, status, active list and rows) in LDS, so the
+// loop never reads rows from HBM, when a member then holds at least 512 rows and the team
+// needs at most TEAM_MAX workgroups; else about 3000 rows per workgroup (at most 16) streamed
+// from HBM.  Never more than the launch's workgroups.
+int team_size(const svm_problem_t* p, const Inspect& in, int workers, int requested) {
+    const int cap = std::max(1, std::min(TEAM_MAX, workers));
+    if (requested > 0) return std::min(requested, cap);
+    const bool dense = p->layout != SVM_CSR;
+    const int W = dense ? dpad4(p->d) : p->d;
+    const double fixed = (double)al16(8.0 * W) + al16(4.0 * BATCH_SUMR * W) + 6 * 16;
+    const double avail = (double)BATCH_LDS_BYTES - fixed;
+    const double avg = dense ? 0.0 : (double)in.nnz / (double)p->n;
+    const double per_row = 11.0 + (dense ? 4.0 * dpad4(p->d) : 4.0 + avg * (in.pattern ? 2.0 : 6.0));
+    const double rows_cap = avail / per_row * (dense ? 0.97 : 0.85);   // CSR segments vary in length
+    // each member pays a fixed cost per iteration (pair staging, block reduction, team exchange:
+    // about 7 us); residency pays off when a member holds at least 512 rows (CSR and narrow
+    // dense rows), while wide dense rows stream from HBM at a cost per row close to LDS's
+    if (rows_cap >= 512.0) {
+        const int b = (int)std::ceil((double)p->n / rows_cap);
+        if (b <= cap) return std::max(1, b);
+    }
+    return std::max(1, std::min(std::min(16, cap), (p->n + 2999) / 3000));
 }
 
 int64_t shrink_h(const svm_params_t* q, int n) {
@@ -115,9 +146,8 @@ int64_t shrink_h(const svm_params_t* q, int n) {
     return (int64_t)std::max(1.0, h);
 }
 
-// Validate on the device and fill a descriptor; `ws` holds prob_bytes(p) bytes.
-int prepare(const svm_problem_t* p, const svm_params_t* q, int team, double* alpha, double* f_user,
-            unsigned char* ws, BatchResult* res, Ctl* vctl, hipStream_t s, BatchDesc* D) {
+// Validate on the device and learn the CSR nonzero count and whether every value is 1.0.
+int inspect(const svm_problem_t* p, Ctl* vctl, hipStream_t s, Inspect* out) {
     hipError_t e = hipMemsetAsync(vctl, 0, sizeof(Ctl), s);
     if (e == hipSuccess)
         e = launch_validate(p->n, p->d, p->layout, p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR, p->row_ptr,
@@ -133,7 +163,26 @@ int prepare(const svm_problem_t* p, const svm_params_t* q, int team, double* alp
     if (h.err & 2) return SVM_ENONFINITE;
     if (h.n_pos == 0 || h.n_neg == 0) return SVM_EONECLASS;
     if (p->layout == SVM_CSR && h.max_row_nnz > 4096) return SVM_EUNSUPPORTED;
-    const ProbBytes b = prob_bytes(p, f_user == nullptr, team);
+    *out = Inspect{};
+    if (p->layout == SVM_CSR) {
+        int32_t* flag = reinterpret_cast<int32_t*>(vctl) + 40;
+        e = launch_check_pattern(nnz, p->val, flag, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&notpat, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return SVM_EHIP;
+        out->nnz = nnz;
+        out->pattern = notpat == 0;
+    }
+    return SVM_OK;
+}
+
+// Fill the descriptor of a solve (host only).  `base` / `teamp` hold the two parts of
+// prob_bytes(p, f_user == nullptr, team, rec_members); dense rows are already packed at
+// base + x and the team records zeroed.
+void fill_desc(const svm_problem_t* p, const svm_params_t* q, const Inspect& in, int team, int rec_members,
+               double* alpha, double* f_user, unsigned char* base, unsigned char* teamp, BatchResult* res,
+               BatchDesc* D) {
+    const ProbBytes b = prob_bytes(p, f_user == nullptr, team, rec_members);
     memset(D, 0, sizeof(*D));
     D->n = p->n;
     D->d = p->d;
@@ -144,20 +193,12 @@ int prepare(const svm_problem_t* p, const svm_params_t* q, int team, double* alp
         D->row_ptr = p->row_ptr;
         D->col = p->col;
         D->val = p->val;
-        int32_t* flag = reinterpret_cast<int32_t*>(vctl) + 40;
-        e = launch_check_pattern(nnz, p->val, flag, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(&notpat, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return SVM_EHIP;
-        D->pattern_only = notpat == 0;
+        D->pattern_only = in.pattern;
     } else {
         D->lay = LAY_DENSE;
-        float* xp = reinterpret_cast<float*>(ws + b.x);
-        e = launch_pack_dense(p->n, p->d, D->dpad, p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR, xp, s);
-        if (e != hipSuccess) return SVM_EHIP;
-        D->x = xp;
+        D->x = reinterpret_cast<float*>(base + b.x);
     }
-    const double avg = p->layout == SVM_CSR ? (double)nnz / (double)p->n : 0.0;
+    const double avg = p->layout == SVM_CSR ? (double)in.nnz / (double)p->n : 0.0;
     D->lpr = tune_lanes_per_row(p, avg, q->kernel_precision, q->lanes_per_row);
     D->C = q->C;
     D->gamma = q->gamma;
@@ -168,18 +209,31 @@ int prepare(const svm_problem_t* p, const svm_params_t* q, int team, double* alp
     D->max_iter = q->max_iter;
     D->flags = q->flags;
     D->alpha = alpha;
-    D->f = f_user ? f_user : reinterpret_cast<double*>(ws + b.f);
-    D->status = ws + b.status;
-    D->act = reinterpret_cast<int32_t*>(ws + b.act);
-    D->list_w = reinterpret_cast<int32_t*>(ws + b.lw);
-    D->list_z = reinterpret_cast<int32_t*>(ws + b.lz);
-    D->coef = reinterpret_cast<double*>(ws + b.coef);
+    D->f = f_user ? f_user : reinterpret_cast<double*>(base + b.f);
+    D->status = base + b.status;
+    D->act = reinterpret_cast<int32_t*>(base + b.act);
+    D->list_w = reinterpret_cast<int32_t*>(base + b.lw);
+    D->list_z = reinterpret_cast<int32_t*>(teamp + b.lz);
+    D->coef = reinterpret_cast<double*>(teamp + b.coef);
     D->team = team;
-    D->trec = reinterpret_cast<unsigned long long*>(ws + b.trec);
+    D->trec = reinterpret_cast<unsigned long long*>(base + b.trec);
     D->prof = debug_profile_slots();
     D->res = res;
-    e = hipMemsetAsync(D->trec, 0, sizeof(unsigned long long) * 2 * 16 * team, s);
-    return e == hipSuccess ? SVM_OK : SVM_EHIP;
+}
+
+// Batch entry: pack dense rows and zero the team records with kernels on `s` (no loop is
+// running yet), then fill the descriptor.  `ws` holds the base part followed by the team part.
+int prepare(const svm_problem_t* p, const svm_params_t* q, const Inspect& in, int team, double* alpha,
+            double* f_user, unsigned char* ws, BatchResult* res, hipStream_t s, BatchDesc* D) {
+    const ProbBytes b = prob_bytes(p, f_user == nullptr, team, team);
+    hipError_t e = hipSuccess;
+    if (p->layout != SVM_CSR)
+        e = launch_pack_dense(p->n, p->d, dpad4(p->d), p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR,
+                              reinterpret_cast<float*>(ws + b.x), s);
+    if (e == hipSuccess) e = hipMemsetAsync(ws + b.trec, 0, sizeof(unsigned long long) * 2 * 16 * team, s);
+    if (e != hipSuccess) return SVM_EHIP;
+    fill_desc(p, q, in, team, team, alpha, f_user, ws, ws + b.base, res, D);
+    return SVM_OK;
 }
 
 void fill_result(const BatchResult& r, int team, svm_result_t* out) {
@@ -244,7 +298,7 @@ struct Arena {
 };
 
 constexpr int RING = 4096;          // descriptor slots
-constexpr int TRING = RING * 16;    // worker tickets
+constexpr int TRING = RING * 32;    // worker tickets
 
 struct Pending {
     int64_t ticket;
@@ -253,20 +307,30 @@ struct Pending {
     double* alpha;
 };
 
+// A problem between admission and completion.
+struct Job {
+    Pending w;
+    int32_t slot = -1;                // descriptor slot of its current job (preparation, then solve)
+    size_t base_off = 0, base_bytes = 0, team_off = 0, team_bytes = 0;
+    Inspect in;
+    int team = 1;
+    bool counted_deferred = false;
+};
+
 struct Server {
     size_t budget = 0;
     int max_slots = 0;
     int workgroups = 0;
-    hipStream_t ks = nullptr, cs = nullptr;
+    hipStream_t ks = nullptr;
     unsigned char* arena_mem = nullptr;
     Arena arena;
     BatchDesc* ring = nullptr;        // pinned
     int2* tickets = nullptr;          // pinned
-    BatchResult* results = nullptr;   // pinned
+    BatchResult* results = nullptr;   // pinned, per descriptor slot
+    PrepOut* preps = nullptr;         // pinned, per descriptor slot
     int32_t* tail = nullptr;          // pinned
     int32_t* shutdown = nullptr;      // pinned
     int32_t* head = nullptr;          // device: [0] next ticket, [16..17] tail / shutdown mirrors
-    Ctl* vctl = nullptr;              // device scratch for validation
     int32_t published = 0;            // descriptors
     int32_t published_tickets = 0;    // worker tickets
     bool kernel_live = false;
@@ -274,34 +338,16 @@ struct Server {
     double last_busy_ms = 0.0;
     std::thread monitor;
     std::mutex mu;
-    struct Live {
-        int32_t slot, team;
-        size_t off, bytes;
-    };
-    std::map<int64_t, Live> live;     // ticket -> resources (published, not yet observed done)
+    std::deque<Pending> waiting;      // not admitted yet (slots or memory)
+    std::map<int64_t, Job> prepping;  // preparation job published
+    std::deque<Job> ready;            // prepared, waiting for the team part's memory
+    std::map<int64_t, Job> live;      // solve published, not yet observed done
     std::map<int64_t, svm_result_t> done;
-    std::map<int64_t, int> failed;    // ticket -> error code (rejected at admission)
-    std::deque<Pending> waiting;
-    std::map<int64_t, int32_t> ticket_slot;
+    std::map<int64_t, int> failed;    // ticket -> error code
     int64_t next_ticket = 0;
     int64_t n_admitted = 0, n_deferred = 0, n_completed = 0;
 
-    // move problems whose done flag is set out of `live`
-    void scan_done() {
-        for (auto it = live.begin(); it != live.end();) {
-            BatchResult& r = results[it->second.slot];
-            if (__atomic_load_n(&r.done, __ATOMIC_ACQUIRE)) {
-                svm_result_t out;
-                fill_result(r, it->second.team, &out);
-                done[it->first] = out;
-                arena.release(it->second.off, it->second.bytes);
-                ++n_completed;
-                it = live.erase(it);
-            } else {
-                ++it;
-            }
-        }
-    }
+    int in_flight() const { return (int)(prepping.size() + ready.size() + live.size()); }
 
     // The loop is stopped only by the host (park or destroy), and only when no published ticket
     // is waiting, so a new launch starts its tickets at the published count.
@@ -324,65 +370,149 @@ struct Server {
         if (launch_batch(a, workgroups, SVM_KERNEL_FP32, ks) == hipSuccess) kernel_live = true;
     }
 
-    // stop the loop once every published problem is done (its workgroups return to the GPU)
+    // stop the loop once nothing is in flight (its workgroups return to the GPU)
     void park() {
-        if (!kernel_live || !live.empty()) return;
+        if (!kernel_live || in_flight() || !waiting.empty()) return;
         __atomic_store_n(shutdown, 1, __ATOMIC_RELEASE);
         (void)hipStreamSynchronize(ks);
         __atomic_store_n(shutdown, 0, __ATOMIC_RELEASE);
         kernel_live = false;
     }
 
-    // publish one admitted problem; returns an error code for rejected problems
-    int publish(int64_t ticket, const svm_problem_t* p, const svm_params_t* q, double* alpha, size_t off,
-                size_t bytes, int team) {
+    // hand descriptor D and `team` tickets (rank -1: one preparation ticket) to the loop
+    int32_t publish(const BatchDesc& D, int team, bool prep) {
         const int32_t slot = published & (RING - 1);
-        BatchDesc D;
-        memset(&results[slot], 0, sizeof(BatchResult));
-        int rc = prepare(p, q, team, alpha, nullptr, arena_mem + off, &results[slot], vctl, cs, &D);
-        if (rc) return rc;
-        if (hipStreamSynchronize(cs) != hipSuccess) return SVM_EHIP;   // packing done before publishing
         ring[slot] = D;
-        for (int r = 0; r < team; ++r) tickets[(published_tickets + r) & (TRING - 1)] = make_int2(slot, r);
+        if (prep) {
+            tickets[published_tickets & (TRING - 1)] = make_int2(slot, -1);
+        } else {
+            for (int r = 0; r < team; ++r) tickets[(published_tickets + r) & (TRING - 1)] = make_int2(slot, r);
+        }
         std::atomic_thread_fence(std::memory_order_release);
         ++published;
-        published_tickets += team;
+        published_tickets += prep ? 1 : team;
         __atomic_store_n(tail, published_tickets, __ATOMIC_RELEASE);
-        live[ticket] = Live{slot, team, off, bytes};
-        last_busy_ms = now_ms();
-        ticket_slot[ticket] = slot;
-        ++n_admitted;
         ensure_running();
-        return SVM_OK;
+        return slot;
     }
 
-    bool try_admit(const Pending& w) {
-        const int team = team_size(w.prob.n, workgroups, w.params.grid_blocks);
-        const size_t bytes = prob_bytes(&w.prob, true, team).total;
-        if ((int)live.size() >= max_slots) return false;
-        size_t off = 0;
-        if (!arena.alloc(bytes, &off)) return false;
-        const int rc = publish(w.ticket, &w.prob, &w.params, w.alpha, off, bytes, team);
-        if (rc) {
-            arena.release(off, bytes);
-            failed[w.ticket] = rc;
-        }
+    // waiting -> prepping: needs a slot and the base part of the solver state
+    bool start_prep(const Pending& w) {
+        if (in_flight() >= max_slots) return false;
+        Job j;
+        j.w = w;
+        j.base_bytes = prob_bytes(&w.prob, true, 1, TEAM_MAX).base;
+        if (!arena.alloc(j.base_bytes, &j.base_off)) return false;
+        const ProbBytes b = prob_bytes(&w.prob, true, 1, TEAM_MAX);
+        unsigned char* base = arena_mem + j.base_off;
+        const int32_t slot = published & (RING - 1);
+        memset(&preps[slot], 0, sizeof(PrepOut));
+        BatchDesc D;
+        memset(&D, 0, sizeof(D));
+        D.n = w.prob.n;
+        D.d = w.prob.d;
+        D.dpad = dpad4(w.prob.d);
+        D.lay = w.prob.layout == SVM_CSR ? LAY_CSR_TABLE : LAY_DENSE;
+        D.y = w.prob.y;
+        D.row_ptr = w.prob.row_ptr;
+        D.col = w.prob.col;
+        D.val = w.prob.val;
+        D.x = w.prob.layout == SVM_CSR ? nullptr : reinterpret_cast<float*>(base + b.x);
+        D.xsrc = w.prob.x;
+        D.ldx = w.prob.ldx;
+        D.src_layout = w.prob.layout;
+        D.trec = reinterpret_cast<unsigned long long*>(base + b.trec);
+        D.prep = &preps[slot];
+        j.slot = publish(D, 1, true);
+        prepping.emplace(w.ticket, j);
         return true;
+    }
+
+    // prepping -> ready or failed
+    void scan_prep() {
+        for (auto it = prepping.begin(); it != prepping.end();) {
+            const PrepOut& o = preps[it->second.slot];
+            if (!__atomic_load_n(&o.done, __ATOMIC_ACQUIRE)) {
+                ++it;
+                continue;
+            }
+            Job j = it->second;
+            it = prepping.erase(it);
+            int rc = SVM_OK;
+            if (o.err & 1) rc = SVM_EINVAL;
+            else if (o.err & 2) rc = SVM_ENONFINITE;
+            else if (o.n_pos == 0 || o.n_neg == 0) rc = SVM_EONECLASS;
+            else if (j.w.prob.layout == SVM_CSR && o.max_row_nnz > 4096) rc = SVM_EUNSUPPORTED;
+            if (rc) {
+                arena.release(j.base_off, j.base_bytes);
+                failed[j.w.ticket] = rc;
+                continue;
+            }
+            j.in.nnz = o.nnz;
+            j.in.pattern = o.pattern;
+            j.team = team_size(&j.w.prob, j.in, workgroups, j.w.params.grid_blocks);
+            while (j.team > 1 && j.base_bytes + prob_bytes(&j.w.prob, true, j.team, TEAM_MAX).team > budget) j.team /= 2;
+            j.team_bytes = prob_bytes(&j.w.prob, true, j.team, TEAM_MAX).team;
+            ready.push_back(j);
+        }
+    }
+
+    // ready -> live: needs the team part of the solver state
+    void start_solves() {
+        while (!ready.empty()) {
+            Job& j = ready.front();
+            if (!arena.alloc(j.team_bytes, &j.team_off)) {
+                if (!j.counted_deferred) {
+                    j.counted_deferred = true;
+                    ++n_deferred;
+                }
+                return;
+            }
+            const int32_t slot = published & (RING - 1);
+            memset(&results[slot], 0, sizeof(BatchResult));
+            BatchDesc D;
+            fill_desc(&j.w.prob, &j.w.params, j.in, j.team, TEAM_MAX, j.w.alpha, nullptr, arena_mem + j.base_off,
+                      arena_mem + j.team_off, &results[slot], &D);
+            j.slot = publish(D, j.team, false);
+            ++n_admitted;
+            live.emplace(j.w.ticket, j);
+            ready.pop_front();
+        }
+    }
+
+    // live -> done
+    void scan_done() {
+        for (auto it = live.begin(); it != live.end();) {
+            BatchResult& r = results[it->second.slot];
+            if (__atomic_load_n(&r.done, __ATOMIC_ACQUIRE)) {
+                svm_result_t out;
+                fill_result(r, it->second.team, &out);
+                done[it->first] = out;
+                arena.release(it->second.base_off, it->second.base_bytes);
+                arena.release(it->second.team_off, it->second.team_bytes);
+                ++n_completed;
+                it = live.erase(it);
+            } else {
+                ++it;
+            }
+        }
     }
 
     void harvest() {
         scan_done();
-        while (!waiting.empty() && try_admit(waiting.front())) waiting.pop_front();
-        if (!live.empty()) last_busy_ms = now_ms();
+        scan_prep();
+        start_solves();
+        while (!waiting.empty() && start_prep(waiting.front())) waiting.pop_front();
+        if (in_flight() || !waiting.empty()) last_busy_ms = now_ms();
     }
 
     void monitor_loop() {
         for (;;) {
-            std::this_thread::sleep_for(std::chrono::milliseconds(20));
+            std::this_thread::sleep_for(std::chrono::milliseconds(2));
             std::lock_guard<std::mutex> lk(mu);
             if (stop_monitor) return;
             harvest();
-            if (kernel_live && live.empty() && waiting.empty() && now_ms() - last_busy_ms > 2000.0) park();
+            if (kernel_live && !in_flight() && waiting.empty() && now_ms() - last_busy_ms > 2000.0) park();
         }
     }
 };
@@ -403,25 +533,34 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
         if (!alpha[p] || params[p].kernel_precision != kprec) return SVM_EINVAL;
     }
     // one buffer for every problem's solver state, descriptors and results
-    const int wg = std::max(1, std::min(16 * k, batch_max_workgroups(kprec)));
+    const int wg = std::max(1, batch_max_workgroups(kprec));
     std::vector<int> team(k);
+    std::vector<Inspect> ins(k);
     int64_t nt = 0;
+    Ctl* ictl = nullptr;
+    if (hipMalloc(&ictl, sizeof(Ctl) + 256) != hipSuccess) return SVM_ENOMEM;
     for (int p = 0; p < k; ++p) {
-        team[p] = team_size(probs[p].n, wg, params[p].grid_blocks);
+        const int rc = inspect(&probs[p], ictl, s, &ins[p]);
+        if (rc) {
+            (void)hipFree(ictl);
+            return rc;
+        }
+        team[p] = team_size(&probs[p], ins[p], wg, params[p].grid_blocks);
         nt += team[p];
     }
+    (void)hipFree(ictl);
     std::vector<size_t> off(k);
     size_t o = al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) + al(sizeof(Ctl) + 256) + al(64) +
                al(sizeof(int2) * nt);
     for (int p = 0; p < k; ++p) {
         off[p] = o;
-        o += prob_bytes(&probs[p], !(f && f[p]), team[p]).total;
+        const ProbBytes b = prob_bytes(&probs[p], !(f && f[p]), team[p], team[p]);
+        o += b.base + b.team;
     }
     unsigned char* buf = nullptr;
     if (hipMalloc(&buf, o) != hipSuccess) return SVM_ENOMEM;
     BatchDesc* ddesc = reinterpret_cast<BatchDesc*>(buf);
     BatchResult* dres = reinterpret_cast<BatchResult*>(buf + al(sizeof(BatchDesc) * k));
-    Ctl* vctl = reinterpret_cast<Ctl*>(buf + al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k));
     int32_t* head = reinterpret_cast<int32_t*>(buf + al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) +
                                                al(sizeof(Ctl) + 256));
     int2* dtk = reinterpret_cast<int2*>(buf + al(sizeof(BatchDesc) * k) + al(sizeof(BatchResult) * k) +
@@ -429,7 +568,7 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
     std::vector<BatchDesc> hd(k);
     int rc = SVM_OK;
     for (int p = 0; p < k && rc == SVM_OK; ++p)
-        rc = prepare(&probs[p], &params[p], team[p], alpha[p], f ? f[p] : nullptr, buf + off[p], dres + p, vctl, s,
+        rc = prepare(&probs[p], &params[p], ins[p], team[p], alpha[p], f ? f[p] : nullptr, buf + off[p], dres + p, s,
                      &hd[p]);
     if (rc) {
         (void)hipStreamSynchronize(s);
@@ -483,23 +622,24 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
 }
 
 int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server) {
-    if (!server || max_slots < 1 || max_slots > RING / 2 || hbm_budget < 4096) return SVM_EINVAL;
+    if (!server || max_slots < 1 || max_slots > RING / 4 || hbm_budget < 4096) return SVM_EINVAL;
     Server* S = new Server();
     S->budget = hbm_budget;
     S->max_slots = max_slots;
-    // the loop leaves 8 compute units free: admission validates and packs each problem with small
-    // kernels on another stream while the loop runs
+    // the loop leaves 8 compute units free for the caller's other work (copies, kernels); its own
+    // admission work (validation, packing) runs inside the loop
     const int cus = device_cu_count(), per_cu = cus > 0 ? batch_max_workgroups(SVM_KERNEL_FP32) / cus : 0;
     S->workgroups = std::max(1, per_cu * std::max(1, cus - 8));
-    bool ok = hipStreamCreateWithFlags(&S->ks, hipStreamNonBlocking) == hipSuccess &&
-              hipStreamCreateWithFlags(&S->cs, hipStreamNonBlocking) == hipSuccess &&
+    bool ok = S->workgroups >= TEAM_MAX &&
+              hipStreamCreateWithFlags(&S->ks, hipStreamNonBlocking) == hipSuccess &&
               hipMalloc(&S->arena_mem, hbm_budget) == hipSuccess &&
               hipHostMalloc((void**)&S->ring, sizeof(BatchDesc) * RING, hipHostMallocCoherent) == hipSuccess &&
               hipHostMalloc((void**)&S->tickets, sizeof(int2) * TRING, hipHostMallocCoherent) == hipSuccess &&
               hipHostMalloc((void**)&S->results, sizeof(BatchResult) * RING, hipHostMallocCoherent) == hipSuccess &&
+              hipHostMalloc((void**)&S->preps, sizeof(PrepOut) * RING, hipHostMallocCoherent) == hipSuccess &&
               hipHostMalloc((void**)&S->tail, 64, hipHostMallocCoherent) == hipSuccess &&
               hipHostMalloc((void**)&S->shutdown, 64, hipHostMallocCoherent) == hipSuccess &&
-              hipMalloc(&S->head, 256) == hipSuccess && hipMalloc(&S->vctl, sizeof(Ctl) + 256) == hipSuccess;
+              hipMalloc(&S->head, 256) == hipSuccess;
     if (!ok) {
         svm_server_destroy(S);
         return SVM_ENOMEM;
@@ -508,6 +648,7 @@ int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server) {
     *S->tail = 0;
     *S->shutdown = 0;
     memset(S->results, 0, sizeof(BatchResult) * RING);
+    memset(S->preps, 0, sizeof(PrepOut) * RING);
     S->ensure_running();
     if (!S->kernel_live) {
         svm_server_destroy(S);
@@ -526,16 +667,20 @@ int svm_server_submit(void* server, const svm_problem_t* prob, const svm_params_
     int rc = check_batch_problem(prob, params);
     if (rc) return rc;
     if (params->kernel_precision != SVM_KERNEL_FP32) return SVM_EINVAL;
-    if (prob_bytes(prob, true, team_size(prob->n, S->workgroups, params->grid_blocks)).total > S->budget) return SVM_ENOMEM;
     std::lock_guard<std::mutex> lk(S->mu);
     Pending w{S->next_ticket++, *prob, *params, alpha};
     *ticket = w.ticket;
+    const ProbBytes b = prob_bytes(prob, true, 1, TEAM_MAX);
+    if (b.base + b.team > S->budget) {      // reported by svm_server_poll for this ticket
+        S->failed[w.ticket] = SVM_ENOMEM;
+        return SVM_OK;
+    }
     S->harvest();
-    S->ensure_running();
-    if (!S->waiting.empty() || !S->try_admit(w)) {
+    if (!S->waiting.empty() || !S->start_prep(w)) {
         S->waiting.push_back(w);
         ++S->n_deferred;
     }
+    S->last_busy_ms = now_ms();
     return SVM_OK;
 }
 
@@ -559,7 +704,7 @@ int svm_server_drain(void* server) {
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->harvest();
-            if (S->live.empty() && S->waiting.empty()) return SVM_OK;
+            if (!S->in_flight() && S->waiting.empty()) return SVM_OK;
         }
         std::this_thread::sleep_for(std::chrono::microseconds(200));
     }
@@ -573,7 +718,7 @@ int svm_server_stats(void* server, int64_t* admitted, int64_t* deferred, int64_t
     if (admitted) *admitted = S->n_admitted;
     if (deferred) *deferred = S->n_deferred;
     if (completed) *completed = S->n_completed;
-    if (in_flight) *in_flight = (int64_t)S->live.size();
+    if (in_flight) *in_flight = (int64_t)S->in_flight();
     return SVM_OK;
 }
 
@@ -589,17 +734,15 @@ int svm_server_destroy(void* server) {
     }
     if (S->shutdown) __atomic_store_n(S->shutdown, 1, __ATOMIC_RELEASE);
     if (S->ks) (void)hipStreamSynchronize(S->ks);
-    if (S->cs) (void)hipStreamSynchronize(S->cs);
     if (S->arena_mem) (void)hipFree(S->arena_mem);
     if (S->head) (void)hipFree(S->head);
-    if (S->vctl) (void)hipFree(S->vctl);
     if (S->ring) (void)hipHostFree(S->ring);
     if (S->tickets) (void)hipHostFree(S->tickets);
     if (S->results) (void)hipHostFree(S->results);
+    if (S->preps) (void)hipHostFree(S->preps);
     if (S->tail) (void)hipHostFree(S->tail);
     if (S->shutdown) (void)hipHostFree(S->shutdown);
     if (S->ks) (void)hipStreamDestroy(S->ks);
-    if (S->cs) (void)hipStreamDestroy(S->cs);
     delete S;
     return SVM_OK;
 }

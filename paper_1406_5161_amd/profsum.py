@@ -3,7 +3,8 @@
     python -m paper_1406_5161_amd.profsum trace DIR [--kernel SUBSTR] [--last N]
     python -m paper_1406_5161_amd.profsum pmc DIR [--kernel SUBSTR] [--last N]
     python -m paper_1406_5161_amd.profsum traffic --fetch DIR --write DIR --calib-fetch DIR
-        --calib-write DIR --calib-bytes B --kernel SUBSTR [--last N] [--source FILE ...] [--out JSON]
+        --calib-write DIR --calib-bytes B --kernel SUBSTR [--last N] [--source FILE ...]
+        [--workload NAME] [--out JSON]
 
 Reads either the SQLite database rocprofv3 writes by default (its `kernels` and
 `pmc_events` views) or its CSV files (`*_kernel_trace.csv`,
@@ -155,7 +156,7 @@ def cmd_traffic(a):
     cwn, cw = _calib_kib(a.calib_write, "WRITE_SIZE")
     sf = a.calib_bytes / (cf * 1024.0)
     sw = a.calib_bytes / (cw * 1024.0)
-    out = {"kernel": a.kernel, "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+    out = {"kernel": a.kernel, "workload": a.workload, "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
            "dispatches": [nf, nw], "calib_kernel": [cfn, cwn], "calib_bytes": a.calib_bytes,
            "calib_fetch_kib": cf, "calib_write_kib": cw, "fetch_scale": sf, "write_scale": sw,
            "hbm_bytes_per_launch": fk * 1024.0 * sf + wk * 1024.0 * sw,
@@ -180,6 +181,7 @@ def main():
     ap.add_argument("--calib-bytes", type=float)
     ap.add_argument("--source", nargs="*")
     ap.add_argument("--out")
+    ap.add_argument("--workload", default=None, help="name of the workload the counters were taken on")
     a = ap.parse_args()
     {"trace": cmd_trace, "pmc": cmd_pmc, "traffic": cmd_traffic}[a.mode](a)
 
