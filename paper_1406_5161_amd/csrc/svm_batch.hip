@@ -199,6 +199,38 @@ DEV void rows_dist(bool dense, int dpad, const float* xb, const OT* off, const C
     }
 }
 
+// Distances of RPT bitset rows (LAY_BITS, one lane per row) to the two pair rows held at pb
+// (pair row u in words [0, wpr), row l in [wpr, 2 wpr)).  Counts are exact integers, so the
+// values equal the CSR path's sums of 1.0 in either precision.
+template <typename KT, int RPT>
+DEV void rows_dist_bits(int wpr, const uint32_t* src, const uint32_t* pb, const int* ri, const bool* vv, KT nuu,
+                        KT nll, KT* du2, KT* dl2) {
+    const uint4* pu = reinterpret_cast<const uint4*>(pb);
+    const uint4* pl = reinterpret_cast<const uint4*>(pb + wpr);
+    int nn[RPT], su[RPT], sl[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) { nn[r] = 0; su[r] = 0; sl[r] = 0; }
+    for (int w4 = 0; w4 < wpr / 4; ++w4) {
+        const uint4 a = pu[w4], b = pl[w4];
+        uint4 v[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            v[r] = vv[r] ? reinterpret_cast<const uint4*>(src + (size_t)ri[r] * wpr)[w4] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            nn[r] += __popc(v[r].x) + __popc(v[r].y) + __popc(v[r].z) + __popc(v[r].w);
+            su[r] += __popc(v[r].x & a.x) + __popc(v[r].y & a.y) + __popc(v[r].z & a.z) + __popc(v[r].w & a.w);
+            sl[r] += __popc(v[r].x & b.x) + __popc(v[r].y & b.y) + __popc(v[r].z & b.z) + __popc(v[r].w & b.w);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        KT a = (KT)nn[r] + nuu - (KT)2 * (KT)su[r], b = (KT)nn[r] + nll - (KT)2 * (KT)sl[r];
+        du2[r] = a < (KT)0 ? (KT)0 : a;
+        dl2[r] = b < (KT)0 ? (KT)0 : b;
+    }
+}
+
 // Local selection over this member's active list from (f, alpha, y) in global memory; every
 // thread gets the result.
 DEV void select_block(const BatchDesc& P, const int32_t* act, int nact, BatchShared& sh, double& bu, int& iu,
@@ -403,8 +435,70 @@ __device__ __attribute__((noinline)) void kernel_sum_block(const BatchDesc& P, c
                                                           BatchShared& sh) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const bool dense = P.lay == LAY_DENSE;
-    const int W = dense ? P.dpad : P.d;
     const KT gam = (KT)P.gamma;
+    if (P.lay == LAY_BITS) {
+        // target rows' bitsets in LDS; one support vector per lane and step
+        const int wpr = P.wpr;
+        uint32_t* tb = reinterpret_cast<uint32_t*>(tile);
+        for (int r0 = 0; r0 < na; r0 += SUMR) {
+            const int nr = min(SUMR, na - r0);
+            for (int e = tid; e < SUMR * wpr; e += BB) {
+                const int r = e / wpr, k = e % wpr;
+                const int a = r < nr ? (rows ? rows[r0 + r] : row0 + r0 + r) : -1;
+                tb[e] = a >= 0 ? P.bits[(size_t)a * wpr + k] : 0u;
+            }
+            __syncthreads();
+            if (tid < SUMR) {
+                int c = 0;
+                for (int k = 0; k < wpr; ++k) c += __popc(tb[tid * wpr + k]);
+                sh.na[tid] = (double)c;
+            }
+            __syncthreads();
+            double acc[SUMR];
+#pragma unroll
+            for (int r = 0; r < SUMR; ++r) acc[r] = 0.0;
+            for (int jb = tid; jb < nz; jb += BB) {
+                const int j = lz[jb];
+                const double cj = lcoef[jb];
+                const uint4* xb = reinterpret_cast<const uint4*>(P.bits + (size_t)j * wpr);
+                int nb = 0, dot[SUMR];
+#pragma unroll
+                for (int r = 0; r < SUMR; ++r) dot[r] = 0;
+                for (int w4 = 0; w4 < wpr / 4; ++w4) {
+                    const uint4 v = xb[w4];
+                    nb += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+#pragma unroll
+                    for (int r = 0; r < SUMR; ++r) {
+                        const uint4 t = reinterpret_cast<const uint4*>(tb + r * wpr)[w4];
+                        dot[r] += __popc(v.x & t.x) + __popc(v.y & t.y) + __popc(v.z & t.z) + __popc(v.w & t.w);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < SUMR; ++r) {
+                    if (r < nr) {
+                        KT d2 = (KT)sh.na[r] + (KT)nb - (KT)2 * (KT)dot[r];
+                        if (d2 < (KT)0) d2 = (KT)0;
+                        acc[r] += cj * (double)kexp(-gam * d2);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < SUMR; ++r) {
+                const double v = wave_sum(acc[r]);
+                if (lane == 0) sh.red[wid][r] = v;
+            }
+            __syncthreads();
+            if (tid < nr) {
+                double v = 0.0;
+                for (int w = 0; w < BNW; ++w) v += sh.red[w][tid];
+                const int a = rows ? rows[r0 + tid] : row0 + r0 + tid;
+                P.f[a] = v - (P.y[a] > 0 ? 1.0 : -1.0);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    const int W = dense ? P.dpad : P.d;
     for (int r0 = 0; r0 < na; r0 += SUMR) {
         const int nr = min(SUMR, na - r0);
         for (int e = tid; e < SUMR * W; e += BB) tile[e] = 0.f;
@@ -510,8 +604,9 @@ __device__ __attribute__((noinline)) void kernel_sum_block(const BatchDesc& P, c
 // One member (rank) of the team of P.team workgroups solving problem P.  Member b owns rows
 // [n b / B, n (b+1) / B); the members run the same driver, take the same decisions from the
 // merged selections, and meet only in team exchanges.
-template <typename KT>
-DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
+// (one instance per kernel precision and row layout, each with its own register allocation)
+template <typename KT, int LAYK>
+__device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned char* dyn) {
     const BatchDesc& P = sh.P;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int n = P.n, B = P.team, rank = sh.rank;
@@ -519,35 +614,40 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
     const int lpr = P.lpr;
     const int NG = BB / lpr, g = tid / lpr, gl = tid % lpr;
     const double C = P.C;
-    const bool dense = P.lay == LAY_DENSE;
+    constexpr bool dense = LAYK == LAY_DENSE;
+    constexpr bool bits = LAYK == LAY_BITS;
     int32_t* act = P.act + seg0;
     int32_t* lw = P.list_w + seg0;
     int32_t* lz = P.list_z + (size_t)rank * n;
     double* lcoef = P.coef + (size_t)rank * n;
     // dynamic LDS: pair rows (float2 per feature), the reconstruction tile (SUMR rows), then,
     // when it fits, this member's segment: f, status, active list and its rows
-    const int W = dense ? P.dpad : P.d;
+    const int W = dense ? P.dpad : bits ? P.wpr : P.d;
     float2* pairv = reinterpret_cast<float2*>(dyn);
+    uint32_t* pairb = reinterpret_cast<uint32_t*>(dyn);   // LAY_BITS: the two pair rows' bitsets
     const size_t tile_off = al16(sizeof(float2) * (size_t)W);
     float* tile = reinterpret_cast<float*>(dyn + tile_off);
     unsigned char* segmem = dyn + tile_off + al16(sizeof(float) * SUMR * (size_t)W);
     const int m = seg1 - seg0;
-    const int nnz0 = dense ? 0 : P.row_ptr[seg0];
-    const int nnz_seg = dense ? 0 : P.row_ptr[seg1] - nnz0;
+    const int nnz0 = (dense || bits) ? 0 : P.row_ptr[seg0];
+    const int nnz_seg = (dense || bits) ? 0 : P.row_ptr[seg1] - nnz0;
     const bool pat = P.pattern_only != 0;
     size_t so = al16(sizeof(double) * (size_t)m);
     double* f_l = reinterpret_cast<double*>(segmem);
     float* x_l = reinterpret_cast<float*>(segmem + so);
+    uint32_t* bits_l = reinterpret_cast<uint32_t*>(segmem + so);
     uint32_t* off_l = reinterpret_cast<uint32_t*>(segmem + so);
     if (dense) {
         so += al16(sizeof(float) * (size_t)m * P.dpad);
+    } else if (bits) {
+        so += al16(sizeof(uint32_t) * (size_t)m * P.wpr);
     } else {
         so += al16(sizeof(uint32_t) * (size_t)(m + 1));
     }
     uint16_t* cols_l = reinterpret_cast<uint16_t*>(segmem + so);
-    if (!dense) so += al16(sizeof(uint16_t) * (size_t)nnz_seg);
+    if (!dense && !bits) so += al16(sizeof(uint16_t) * (size_t)nnz_seg);
     float* vals_l = reinterpret_cast<float*>(segmem + so);
-    if (!dense && !pat) so += al16(sizeof(float) * (size_t)nnz_seg);
+    if (!dense && !bits && !pat) so += al16(sizeof(float) * (size_t)nnz_seg);
     uint8_t* st_l = segmem + so;
     so += al16((size_t)m);
     uint16_t* act_l = reinterpret_cast<uint16_t*>(segmem + so);
@@ -627,6 +727,10 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
             const float4* src = reinterpret_cast<const float4*>(P.x + (size_t)seg0 * P.dpad);
             float4* dst = reinterpret_cast<float4*>(x_l);
             for (int k = tid; k < m * (P.dpad / 4); k += BB) dst[k] = src[k];
+        } else if (bits) {
+            const uint4* src = reinterpret_cast<const uint4*>(P.bits + (size_t)seg0 * P.wpr);
+            uint4* dst = reinterpret_cast<uint4*>(bits_l);
+            for (int k = tid; k < m * (P.wpr / 4); k += BB) dst[k] = src[k];
         } else {
             for (int r = tid; r <= m; r += BB) off_l[r] = (uint32_t)(P.row_ptr[seg0 + r] - nnz0);
             for (int k = tid; k < nnz_seg; k += BB) {
@@ -701,6 +805,24 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
                     }
                     sh.pair[0] = sk;
                 }
+            } else if (bits) {
+                const int wpr = P.wpr;
+                for (int k = tid; k < 2 * wpr; k += BB)
+                    pairb[k] = k < wpr ? P.bits[(size_t)iu * wpr + k] : P.bits[(size_t)il * wpr + (k - wpr)];
+                __syncthreads();
+                if (tid == 0) {
+                    int cu = 0, cl = 0, cd = 0;
+                    for (int k = 0; k < wpr; ++k) {
+                        cu += __popc(pairb[k]);
+                        cl += __popc(pairb[wpr + k]);
+                        cd += __popc(pairb[k] & pairb[wpr + k]);
+                    }
+                    KT d2 = (KT)cu + (KT)cl - (KT)2 * (KT)cd;
+                    if (d2 < (KT)0) d2 = (KT)0;
+                    sh.pair[0] = (double)kexp((KT)(-(KT)P.gamma * d2));
+                    sh.pair[1] = (double)cu;
+                    sh.pair[2] = (double)cl;
+                }
             } else {
                 const int pu0 = P.row_ptr[iu], pu1 = P.row_ptr[iu + 1];
                 const int pl0 = P.row_ptr[il], pl1 = P.row_ptr[il + 1];
@@ -759,7 +881,10 @@ DEV void solve_team(BatchShared& sh, unsigned char* dyn) {
                     ii[r] = seg0 + rr[r];
                 }
                 KT du2[RPT], dl2[RPT];
-                if (res)
+                if (bits)
+                    rows_dist_bits<KT, RPT>(P.wpr, res ? bits_l : P.bits, pairb, res ? rr : ii, vv, nuu, nll, du2,
+                                            dl2);
+                else if (res)
                     rows_dist<KT, RPT>(dense, P.dpad, x_l, off_l, cols_l, vals_l, pat, pairv, rr, vv, gl, lpr, nuu,
                                        nll, du2, dl2);
                 else
@@ -981,6 +1106,28 @@ DEV void prep_job(BatchShared& sh) {
             out[e] = v;
         }
     }
+    if (P.bits) {   // bitset rows for the LAY_BITS path (used only if every value is 1.0)
+        uint32_t* out = const_cast<uint32_t*>(P.bits);
+        const int wpr = P.wpr;
+        for (size_t e = tid; e < (size_t)n * wpr; e += BB) out[e] = 0u;
+        __syncthreads();
+        for (int i = tid; i < n; i += BB) {
+            const int p0 = P.row_ptr[i], p1 = P.row_ptr[i + 1];
+            int cw = -1;
+            uint32_t acc = 0u;
+            for (int p = p0; p < p1; ++p) {
+                const int c = P.col[p];
+                if (c < 0 || c >= d) continue;
+                if ((c >> 5) != cw) {
+                    if (cw >= 0) out[(size_t)i * wpr + cw] |= acc;
+                    cw = c >> 5;
+                    acc = 0u;
+                }
+                acc |= 1u << (c & 31);
+            }
+            if (cw >= 0) out[(size_t)i * wpr + cw] |= acc;
+        }
+    }
     for (int k = tid; k < 2 * 16 * TEAM_MAX; k += BB) P.trec[k] = 0ull;
     if (err) atomicOr(&sh.pr[0], err);
     if (npos) atomicAdd(&sh.pr[1], npos);
@@ -1050,8 +1197,30 @@ __global__ __launch_bounds__(BB) void smo_batch_kernel(BatchArgs A) {
         __syncthreads();
         if (sh.ticket < 0) break;
         if (sh.rank < 0) prep_job(sh);
-        else solve_team<KT>(sh, dyn);
+        else if (sh.P.lay == LAY_DENSE) solve_team<KT, LAY_DENSE>(sh, dyn);
+        else if (sh.P.lay == LAY_BITS) solve_team<KT, LAY_BITS>(sh, dyn);
+        else solve_team<KT, LAY_CSR_TABLE>(sh, dyn);
     }
+}
+
+// Bitset rows from CSR columns (one thread per row; columns increasing, as validated).
+__global__ void pack_bits_kernel(int n, int d, int wpr, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                 uint32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t* o = out + (size_t)i * wpr;
+    for (int k = 0; k < wpr; ++k) o[k] = 0u;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int c = col[p];
+        if (c >= 0 && c < d) o[c >> 5] |= 1u << (c & 31);
+    }
+}
+
+hipError_t launch_pack_bits(int n, int d, int wpr, const int32_t* row_ptr, const int32_t* col, uint32_t* out,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    pack_bits_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, d, wpr, row_ptr, col, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchArgs& a, int workgroups, int kprec, hipStream_t s) {

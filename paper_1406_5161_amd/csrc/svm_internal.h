@@ -11,7 +11,11 @@
 namespace svm {
 
 // sample layouts inside the library
-enum : int { LAY_DENSE = 0, LAY_CSR_TABLE = 1, LAY_CSR_SLOT = 2 };
+// LAY_BITS (batched solver only): CSR rows whose values are all 1.0 with d <= BITS_MAX_D, kept
+// as bitsets of wpr 32-bit words per row; a dot product is a popcount of an AND.
+enum : int { LAY_DENSE = 0, LAY_CSR_TABLE = 1, LAY_CSR_SLOT = 2, LAY_BITS = 3 };
+constexpr int BITS_MAX_D = 1024;
+inline int bits_wpr(int d) { return (((d + 31) / 32) + 3) & ~3; }   // words per row, a multiple of 4
 
 // why a persistent-loop launch returned
 enum : int { EXIT_NONE = 0, EXIT_CONVERGED = 1, EXIT_MAXITER = 2, EXIT_ABORT = 3 };
@@ -197,12 +201,14 @@ struct PrepOut {
 };
 
 struct BatchDesc {
-    int32_t n, d, dpad, lay;             // lay: LAY_DENSE or LAY_CSR_TABLE
+    int32_t n, d, dpad, lay;             // lay: LAY_DENSE, LAY_CSR_TABLE or LAY_BITS
     const float* x;                      // dense, packed [n][dpad]
     const int32_t* row_ptr;
     const int32_t* col;
     const float* val;
     int32_t pattern_only, lpr;           // lpr: lanes per row (dense and CSR)
+    const uint32_t* bits;                // LAY_BITS rows [n][wpr]
+    int32_t wpr, pad5;
     const int8_t* y;
     double C, gamma, eps;
     int32_t shrink_mode, kprec;
@@ -245,6 +251,8 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch(const BatchArgs& a, int workgroups, int kprec, hipStream_t s);
+hipError_t launch_pack_bits(int n, int d, int wpr, const int32_t* row_ptr, const int32_t* col, uint32_t* out,
+                            hipStream_t s);
 unsigned long long* debug_profile_slots();   // per-phase timer slots set by svm_debug_set_profile
 int batch_max_workgroups(int kprec);
 

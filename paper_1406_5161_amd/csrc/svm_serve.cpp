@@ -60,11 +60,14 @@ int tune_lanes_per_row(const svm_problem_t* p, double avg_nnz, int kprec, int re
     return l;
 }
 
+// CSR problems narrow enough for bitset rows (used when every value is 1.0).
+bool bits_capable(const svm_problem_t* p) { return p->layout == SVM_CSR && p->d <= BITS_MAX_D; }
+
 // Solver state of one problem: a base part that does not depend on the team size (packed
 // dense rows, f, status, active and work lists, team records for `rec_members` members) and a
 // team part (each member's support-vector list and coefficients).
 struct ProbBytes {
-    size_t x, f, status, act, lw, trec, base;   // offsets into the base part, its size
+    size_t x, bits, f, status, act, lw, trec, base;   // offsets into the base part, its size
     size_t lz, coef, team;                      // offsets into the team part, its size
 };
 
@@ -74,6 +77,7 @@ ProbBytes prob_bytes(const svm_problem_t* p, bool need_f, int team, int rec_memb
     size_t o = 0;
     auto take = [&](size_t v) { size_t a = o; o = al(o + v); return a; };
     b.x = take(p->layout == SVM_CSR ? 0 : sizeof(float) * n * dpad4(p->d));
+    b.bits = take(bits_capable(p) ? sizeof(uint32_t) * n * bits_wpr(p->d) : 0);
     b.f = take(need_f ? sizeof(double) * n : 0);
     b.status = take(n);
     b.act = take(sizeof(int32_t) * n);
@@ -124,12 +128,15 @@ int team_size(const svm_problem_t* p, const Inspect& in, int workers, int reques
     const int cap = std::max(1, std::min(TEAM_MAX, workers));
     if (requested > 0) return std::min(requested, cap);
     const bool dense = p->layout != SVM_CSR;
-    const int W = dense ? dpad4(p->d) : p->d;
+    const bool bits = bits_capable(p) && in.pattern;
+    const int W = dense ? dpad4(p->d) : bits ? bits_wpr(p->d) : p->d;
     const double fixed = (double)al16(8.0 * W) + al16(4.0 * BATCH_SUMR * W) + 6 * 16;
     const double avail = (double)BATCH_LDS_BYTES - fixed;
     const double avg = dense ? 0.0 : (double)in.nnz / (double)p->n;
-    const double per_row = 11.0 + (dense ? 4.0 * dpad4(p->d) : 4.0 + avg * (in.pattern ? 2.0 : 6.0));
-    const double rows_cap = avail / per_row * (dense ? 0.97 : 0.85);   // CSR segments vary in length
+    const double per_row = 11.0 + (dense ? 4.0 * dpad4(p->d)
+                                   : bits ? 4.0 * bits_wpr(p->d) : 4.0 + avg * (in.pattern ? 2.0 : 6.0));
+    // CSR segments vary in length; dense and bitset rows do not
+    const double rows_cap = avail / per_row * ((dense || bits) ? 0.97 : 0.85);
     // each member pays a fixed cost per iteration (pair staging, block reduction, team exchange:
     // about 7 us); residency pays off when a member holds at least 512 rows (CSR and narrow
     // dense rows), while wide dense rows stream from HBM at a cost per row close to LDS's
@@ -189,17 +196,21 @@ void fill_desc(const svm_problem_t* p, const svm_params_t* q, const Inspect& in,
     D->dpad = dpad4(p->d);
     D->y = p->y;
     if (p->layout == SVM_CSR) {
-        D->lay = LAY_CSR_TABLE;
+        D->lay = bits_capable(p) && in.pattern ? LAY_BITS : LAY_CSR_TABLE;
         D->row_ptr = p->row_ptr;
         D->col = p->col;
         D->val = p->val;
         D->pattern_only = in.pattern;
+        if (bits_capable(p)) {
+            D->bits = reinterpret_cast<uint32_t*>(base + b.bits);
+            D->wpr = bits_wpr(p->d);
+        }
     } else {
         D->lay = LAY_DENSE;
         D->x = reinterpret_cast<float*>(base + b.x);
     }
     const double avg = p->layout == SVM_CSR ? (double)in.nnz / (double)p->n : 0.0;
-    D->lpr = tune_lanes_per_row(p, avg, q->kernel_precision, q->lanes_per_row);
+    D->lpr = D->lay == LAY_BITS ? 1 : tune_lanes_per_row(p, avg, q->kernel_precision, q->lanes_per_row);
     D->C = q->C;
     D->gamma = q->gamma;
     D->eps = q->eps;
@@ -230,6 +241,9 @@ int prepare(const svm_problem_t* p, const svm_params_t* q, const Inspect& in, in
     if (p->layout != SVM_CSR)
         e = launch_pack_dense(p->n, p->d, dpad4(p->d), p->x, p->ldx, p->layout == SVM_DENSE_FEATURE_MAJOR,
                               reinterpret_cast<float*>(ws + b.x), s);
+    if (e == hipSuccess && bits_capable(p) && in.pattern)
+        e = launch_pack_bits(p->n, p->d, bits_wpr(p->d), p->row_ptr, p->col, reinterpret_cast<uint32_t*>(ws + b.bits),
+                             s);
     if (e == hipSuccess) e = hipMemsetAsync(ws + b.trec, 0, sizeof(unsigned long long) * 2 * 16 * team, s);
     if (e != hipSuccess) return SVM_EHIP;
     fill_desc(p, q, in, team, team, alpha, f_user, ws, ws + b.base, res, D);
@@ -423,6 +437,10 @@ struct Server {
         D.src_layout = w.prob.layout;
         D.trec = reinterpret_cast<unsigned long long*>(base + b.trec);
         D.prep = &preps[slot];
+        if (bits_capable(&w.prob)) {
+            D.bits = reinterpret_cast<uint32_t*>(base + b.bits);
+            D.wpr = bits_wpr(w.prob.d);
+        }
         j.slot = publish(D, 1, true);
         prepping.emplace(w.ticket, j);
         return true;
