@@ -68,6 +68,26 @@ def traffic_from_profile(workload):
     return prof.get("hbm_bytes_per_launch")
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def recon_summary(results, data):
+    """Reconstruction / closing-recompute kernel sums over the timed solves: (row, support
+    vector) pairs, their time, and for dense rows on the matrix cores the dot-product flops
+    (2 * dpad per pair) against the FP32 matrix peak."""
+    ms = sum(r.ms_ksum for r in results)
+    pairs = sum(r.recon_pairs for r in results)
+    rec = {"kernel": "kernel_sum_mfma_kernel" if results[-1].ksum_mfma else "kernel_sum_kernel",
+           "ms_per_solve": ms / len(results), "pairs_per_solve": pairs / len(results),
+           "pairs_per_s": pairs / (ms * 1e-3) if ms > 0 else None}
+    if results[-1].ksum_mfma:
+        dpad = (data.d + 3) // 4 * 4
+        tflops = 2.0 * dpad * pairs / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        rec.update({"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tflops / FP32_MFMA_PEAK_TFLOPS})
+    return rec
+
+
 def cpu_baseline(cfg, iters):
     import numpy as np  # noqa: F401
     from oracle import oracle as O
@@ -182,6 +202,7 @@ def main():
                      "launches": launches, "avg_launch_us": loop_ms * 1e3 / max(1, launches),
                      "full_active_set_GBs": full_gbs},
     }
+    out["reconstruction"] = recon_summary(results, data)
     if args.serve:
         out["serving"] = run_serve(args)
     if not args.no_cpu_baseline:

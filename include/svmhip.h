@@ -122,6 +122,9 @@ typedef struct {
     int64_t nnz_streamed;     /* CSR: nonzeros of those rows (0 for dense) */
     int32_t pattern_only;     /* CSR values were all 1.0 and were not read */
     int32_t lanes_per_row;    /* CSR lanes per row used by the step */
+    int32_t ksum_mfma;        /* 1: reconstruction sums ran on the matrix cores (dense, FP32) */
+    double ms_ksum;           /* time in the reconstruction / recompute kernel-sum launches (HIP events) */
+    int64_t recon_pairs;      /* (row, support vector) pairs those launches evaluated */
 } svm_result_t;
 
 /* Bytes of device workspace svm_train needs for this problem (256-byte aligned). */

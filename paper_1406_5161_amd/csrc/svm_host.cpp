@@ -160,17 +160,20 @@ struct Solver {
     double* out6;
     const float* xin;      // dense values the kernels read (packed)
     Ctl h{};                // host mirror of ctl
-    double ms_step = 0, ms_recon = 0;
+    double ms_step = 0, ms_recon = 0, ms_ksum = 0;
+    int64_t recon_pairs = 0;
     int n_launch = 0;
     unsigned long long* work = nullptr;
     StepLds plan_lds{};
     int nseg_max = 0;
     long long nnz_seg_max = 0;
     unsigned long long rows_streamed = 0, nnz_streamed = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
     ~Solver() {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (ev2) (void)hipEventDestroy(ev2);
+        if (ev3) (void)hipEventDestroy(ev3);
     }
 
     template <typename T>
@@ -216,7 +219,10 @@ struct Solver {
         const int W = lay == LAY_DENSE ? dpad : d;
         int R = (int)std::min<size_t>(16, (96 * 1024) / (sizeof(float) * (size_t)W));
         int blocks;
-        if (R < 1) {
+        if (kernel_sum_uses_mfma(a.lay, dpad, q->kernel_precision)) {
+            a.rows_per_block = KSUM_MFMA_ROWS;
+            blocks = (nrows + KSUM_MFMA_ROWS - 1) / KSUM_MFMA_ROWS;
+        } else if (R < 1) {
             // CSR too wide to stage rows in LDS: slot-map densification, one row per workgroup
             a.lay = LAY_CSR_SLOT;
             a.rows_per_block = max_row_nnz;
@@ -229,8 +235,15 @@ struct Solver {
         ns = std::min(ns, std::max(1, nz / 256));
         a.nsplit = ns;
         a.part = part;
+        HIP_TRY(hipEventRecord(ev2, s));
         HIP_TRY(launch_kernel_sum(a, q->kernel_precision, s));
+        HIP_TRY(hipEventRecord(ev3, s));
         HIP_TRY(launch_finish_sum(nrows, ns, part, rows, p->y, 0.0, f, s));
+        HIP_TRY(hipEventSynchronize(ev3));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev2, ev3));
+        ms_ksum += ms;
+        recon_pairs += (int64_t)nrows * nz;
         return SVM_OK;
     }
 
@@ -337,6 +350,8 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
     HIP_TRY(hipMemsetAsync(S.rec, 0, sizeof(Rec) * 2 * MAX_GRID, s));
     HIP_TRY(hipEventCreate(&S.ev0));
     HIP_TRY(hipEventCreate(&S.ev1));
+    HIP_TRY(hipEventCreate(&S.ev2));
+    HIP_TRY(hipEventCreate(&S.ev3));
 
     // ---- validate on the device
     HIP_TRY(hipMemsetAsync(S.ctl, 0, CTL_BYTES, s));
@@ -518,6 +533,10 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
         out->ms_total = now_ms() - t_start;
         out->ms_step = S.ms_step;
         out->ms_recon = S.ms_recon;
+        out->ms_ksum = S.ms_ksum;
+        out->recon_pairs = S.recon_pairs;
+        out->ksum_mfma = kernel_sum_uses_mfma(S.lay == LAY_DENSE ? LAY_DENSE : LAY_CSR_TABLE, S.dpad,
+                                              q->kernel_precision) ? 1 : 0;
         out->rows_streamed = (int64_t)S.rows_streamed;
         out->nnz_streamed = (int64_t)S.nnz_streamed;
         out->pattern_only = S.pattern_only ? 1 : 0;
@@ -613,7 +632,10 @@ int svm_decision(const svm_problem_t* train, const double* alpha, double beta, d
     const int W = dense ? dpad : d;
     int R = (int)std::min<size_t>(16, (96 * 1024) / (sizeof(float) * (size_t)W));
     int blocks;
-    if (R < 1) {
+    if (kernel_sum_uses_mfma(a.lay, dpad, kernel_precision)) {
+        a.rows_per_block = KSUM_MFMA_ROWS;
+        blocks = (nq + KSUM_MFMA_ROWS - 1) / KSUM_MFMA_ROWS;
+    } else if (R < 1) {
         // wide CSR queries: slot-map densification needs the longest query row
         std::vector<int32_t> rp(nq + 1);
         e = hipMemcpyAsync(rp.data(), queries->row_ptr, sizeof(int32_t) * (nq + 1), hipMemcpyDeviceToHost, s);

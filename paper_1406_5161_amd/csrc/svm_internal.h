@@ -159,6 +159,8 @@ hipError_t launch_mark_active(int n, int G, const int32_t* seg_start, const int3
 hipError_t launch_compact(int n, int pred, const uint8_t* mask, const double* alpha, const int8_t* y,
                           int32_t* blk_cnt, int32_t* list, double* coef, int32_t* count_out, hipStream_t s);
 hipError_t launch_kernel_sum(const SumArgs& a, int kprec, hipStream_t s);
+bool kernel_sum_uses_mfma(int lay, int dpad, int kprec);   // dense FP32 sums on the matrix cores
+constexpr int KSUM_MFMA_ROWS = 64;                         // A rows per workgroup of that kernel
 // out[alist[r]] = sum_s part[s][r] + bias (bias: -y[alist[r]] if y != NULL, else -beta)
 hipError_t launch_finish_sum(int na, int nsplit, const double* part, const int32_t* alist, const int8_t* y,
                              double beta, double* out, hipStream_t s);

@@ -507,8 +507,103 @@ __global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_slot_kernel(SumArgs A) {
     }
 }
 
+// Dense rows, FP32 kernel values: the distance terms come from matrix-core products.  A
+// workgroup (4 waves) holds 64 A rows in LDS and sweeps its split of the B list 64 rows at a
+// time; wave w forms the 16 x 64 block of dot products of A rows 16w.. with the chunk through
+// v_mfma_f32_16x16x4f32 (a 16x4 by 4x16 product per instruction, K = dpad in steps of 4), then
+// applies the epilogue d2 = |a|^2 + |b|^2 - 2 a.b (clamped at 0), exp(-gamma d2), and adds
+// coef_b * K into FP64 row sums.  Operand lanes: A[row][k] and B[k][col] sit in lane
+// (row or col) + 16 k; output C[row][col] in lane col + 16 (row / 4), register row % 4.
+constexpr int MF_T = 64;              // A rows per workgroup, B rows per chunk
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int MF_MAX_DPAD = 240;      // LDS: 2 x 64 rows x (dpad + 1) floats
+
+__global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_mfma_kernel(SumArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float s_na[MF_T], s_nb[MF_T];
+    __shared__ double s_cb[MF_T];
+    const int dpad = A.dpad, S = dpad + 1;       // odd row stride: column reads hit distinct banks
+    float* at = reinterpret_cast<float*>(smem);
+    float* bt = at + MF_T * S;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int r0 = blockIdx.x * MF_T;
+    const int nr = min(MF_T, A.na - r0);
+    for (int e = tid; e < MF_T * dpad; e += SUM_BLOCK) {
+        const int r = e / dpad, k = e % dpad;
+        float v = 0.f;
+        if (r < nr) v = A.ax[(size_t)(A.alist ? A.alist[r0 + r] : r0 + r) * dpad + k];
+        at[r * S + k] = v;
+    }
+    __syncthreads();
+    if (tid < MF_T) {
+        float sq = 0.f;
+        for (int k = 0; k < dpad; ++k) sq = fmaf(at[tid * S + k], at[tid * S + k], sq);
+        s_na[tid] = sq;
+    }
+    const float gam = (float)A.gamma;
+    const int per = (A.nb + A.nsplit - 1) / A.nsplit;
+    const int b0 = blockIdx.y * per, b1 = min(A.nb, b0 + per);
+    const int mrow = lane & 15, mk = lane >> 4;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = b0; c0 < b1; c0 += MF_T) {
+        const int nc = min(MF_T, b1 - c0);
+        __syncthreads();                          // the previous chunk is no longer read
+        for (int e = tid; e < MF_T * dpad; e += SUM_BLOCK) {
+            const int c = e / dpad, k = e % dpad;
+            bt[c * S + k] = c < nc ? A.bx[(size_t)A.blist[c0 + c] * dpad + k] : 0.f;
+        }
+        if (tid < MF_T) s_cb[tid] = tid < nc ? A.coef[c0 + tid] : 0.0;
+        __syncthreads();
+        if (tid < MF_T) {
+            float sq = 0.f;
+            for (int k = 0; k < dpad; ++k) sq = fmaf(bt[tid * S + k], bt[tid * S + k], sq);
+            s_nb[tid] = sq;
+        }
+        __syncthreads();
+        const float* arow = at + (16 * wid + mrow) * S + mk;
+        for (int cb = 0; cb < 4; ++cb) {
+            const float* brow = bt + (16 * cb + mrow) * S + mk;
+            f32x4 d = {0.f, 0.f, 0.f, 0.f};
+            for (int k4 = 0; k4 < dpad; k4 += 4)
+                d = __builtin_amdgcn_mfma_f32_16x16x4f32(arow[k4], brow[k4], d, 0, 0, 0);
+            const int col = 16 * cb + mrow;
+            const float nbc = s_nb[col];
+            const double cbv = s_cb[col];
+            const float dv[4] = {d[0], d[1], d[2], d[3]};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * wid + 4 * mk + i;
+                float d2 = s_na[row] + nbc - 2.f * dv[i];
+                d2 = d2 < 0.f ? 0.f : d2;
+                acc[i] += cbv * (double)expf(-gam * d2);
+            }
+        }
+    }
+    // rows 16 wid + 4 mk + i: add the 16 lanes (columns) that share mk
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double v = acc[i];
+        for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+        const int row = 16 * wid + 4 * mk + i;
+        if (mrow == 0 && row < nr) A.part[(size_t)blockIdx.y * A.na + r0 + row] = v;
+    }
+}
+
+bool kernel_sum_uses_mfma(int lay, int dpad, int kprec) {
+    return lay == LAY_DENSE && kprec == SVM_KERNEL_FP32 && dpad <= MF_MAX_DPAD;
+}
+
 hipError_t launch_kernel_sum(const SumArgs& a, int kprec, hipStream_t s) {
     if (a.na <= 0) return hipSuccess;
+    if (kernel_sum_uses_mfma(a.lay, a.dpad, kprec)) {
+        const size_t lds = sizeof(float) * 2 * MF_T * (size_t)(a.dpad + 1);
+        dim3 grid((a.na + MF_T - 1) / MF_T, a.nsplit);
+        SumArgs c = a;
+        (void)hipFuncSetAttribute((const void*)kernel_sum_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        kernel_sum_mfma_kernel<<<grid, SUM_BLOCK, lds, s>>>(c);
+        return hipGetLastError();
+    }
     if (a.lay == LAY_CSR_SLOT) {
         // rows_per_block carries the longest A row here
         const size_t lds = ((sizeof(float) * (size_t)(1 + a.rows_per_block) + 15) & ~(size_t)15) +

@@ -48,7 +48,8 @@ class svm_result_t(C.Structure):
                 ("status", C.c_int32), ("shrink_passes", C.c_int64), ("shrunk_total", C.c_int64),
                 ("n_launches", C.c_int32), ("grid_blocks", C.c_int32), ("ms_total", C.c_double),
                 ("ms_step", C.c_double), ("ms_recon", C.c_double), ("rows_streamed", C.c_int64),
-                ("nnz_streamed", C.c_int64), ("pattern_only", C.c_int32), ("lanes_per_row", C.c_int32)]
+                ("nnz_streamed", C.c_int64), ("pattern_only", C.c_int32), ("lanes_per_row", C.c_int32),
+                ("ksum_mfma", C.c_int32), ("ms_ksum", C.c_double), ("recon_pairs", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -312,6 +312,23 @@ def test_decision_matches_oracle_for_any_alpha(S, layout, prec):
     assert np.abs(dv - dref).max() <= tol
 
 
+@pytest.mark.parametrize("d", [20, 28, 128, 200, 260])
+def test_dense_kernel_sums_on_matrix_cores(S, d):
+    """Dense FP32 kernel sums (decision values, reconstruction) use matrix-core products for
+    dpad <= 240 and the vector path above; both within the decision tolerance of the oracle,
+    over several 64-row tiles, ragged tails and a split support-vector list."""
+    r = np.random.default_rng([1406, 5161, 91, d])
+    data = g.gen_blobs(2300, d, r)
+    q = g.gen_blobs(64 * 9 + 13, d, r)
+    gamma = 0.5 / d
+    alpha = np.where(r.random(data.n) < 0.6, r.uniform(0, 1.0, data.n), 0.0)
+    dv = S.decision_data(data, alpha, -0.25, gamma, q)
+    dref = O.decision(data, alpha, -0.25, gamma, q)
+    err = np.abs(dv - dref).max()
+    P("d", d, "max |decision - oracle|", err)
+    assert err <= 1e-4
+
+
 # ------------------------------------------------------------------ warm start: one step from a given state
 
 def test_one_step_from_oracle_state(S):
