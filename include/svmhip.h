@@ -73,6 +73,7 @@ extern "C" {
 #define SVM_FLAG_NO_FINAL_RECOMPUTE 2u /* skip the closing FP64-accumulated recompute of f and KKT re-check */
 #define SVM_FLAG_NO_LDS_PAYLOAD 4u     /* tuning/test: stream row payload from HBM even when it fits in LDS */
 #define SVM_FLAG_NO_LDS_STATE 8u       /* tuning/test: keep per-row state in HBM as well */
+#define SVM_FLAG_NO_BITSETS 16u        /* tuning/test: binary CSR rows as column ids, not bitsets */
 
 /* A labelled (or, for queries, unlabelled) sample set.  All pointers are device pointers. */
 typedef struct {

@@ -56,8 +56,8 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Plan {
-    size_t ctl, xpack, fint, status, mask, act, seg, cnt, rec, listw, listz, coef, blkcnt, counts, part, sumblk,
-        out6, work, total;
+    size_t ctl, xpack, bits, fint, status, mask, act, seg, cnt, rec, listw, listz, coef, blkcnt, counts, part,
+        sumblk, out6, work, total;
 };
 
 int dpad_of(int d) { return (d + 3) & ~3; }
@@ -73,6 +73,8 @@ Plan make_plan(const svm_problem_t* p) {
     };
     q.ctl = take(CTL_BYTES);
     q.xpack = take(p->layout == SVM_CSR ? 0 : sizeof(float) * n * (size_t)dpad_of(p->d));
+    // binary CSR rows as bitsets (LAY_BITS), reserved for every CSR problem narrow enough
+    q.bits = take(p->layout == SVM_CSR && p->d <= BITS_MAX_D ? sizeof(uint32_t) * n * (size_t)bits_wpr(p->d) : 0);
     q.fint = take(sizeof(double) * n);
     q.status = take(n);
     q.mask = take(n);
@@ -159,6 +161,7 @@ struct Solver {
     double* sumblk;
     double* out6;
     const float* xin;      // dense values the kernels read (packed)
+    uint32_t* bits = nullptr;   // LAY_BITS rows
     Ctl h{};                // host mirror of ctl
     double ms_step = 0, ms_recon = 0, ms_ksum = 0;
     int64_t recon_pairs = 0;
@@ -275,6 +278,8 @@ struct Solver {
         StepArgs a{};
         a.n = n; a.d = d; a.dpad = dpad; a.lay = lay;
         a.x = xin;
+        a.bits = bits;
+        a.wpr = lay == LAY_BITS ? bits_wpr(d) : 0;
         a.row_ptr = p->row_ptr; a.col = p->col; a.val = p->val;
         a.pattern_only = pattern_only ? 1 : 0;
         a.max_row_nnz = max_row_nnz;
@@ -378,6 +383,14 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
         if (S.lay == LAY_CSR_SLOT && S.max_row_nnz > SLOT_MAX_NNZ) return SVM_EUNSUPPORTED;
         S.lpr = q->lanes_per_row ? q->lanes_per_row : 1;   // refined with the LDS plan below
         S.xin = nullptr;
+        if (S.pattern_only && p->d <= BITS_MAX_D && !(q->flags & SVM_FLAG_NO_BITSETS)) {
+            // every value is 1.0: rows as bitsets, dot products as popcounts (exact, so the
+            // same values as the column-table path)
+            S.lay = LAY_BITS;
+            S.lpr = 1;
+            S.bits = S.at<uint32_t>(S.plan.bits);
+            HIP_TRY(launch_pack_bits(p->n, p->d, bits_wpr(p->d), p->row_ptr, p->col, S.bits, s));
+        }
     } else {
         S.lay = LAY_DENSE;
         S.lpr = 1;
@@ -416,7 +429,7 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
             }
         plan = plan_step_lds(S.lay, S.d, S.dpad, S.max_row_nnz, nseg_max, nnz_seg_max, S.pattern_only, max_mode);
         if (plan.total > STEP_LDS_BUDGET) return SVM_EUNSUPPORTED;
-        if (p->layout == SVM_CSR && !q->lanes_per_row) {
+        if (p->layout == SVM_CSR && S.lay != LAY_BITS && !q->lanes_per_row) {
             // rows in LDS: few lanes per row (short LDS chains, no cross-lane reduction);
             // rows from HBM: enough lanes for coalesced row reads
             int l = 1;

@@ -97,13 +97,16 @@ struct StepArgs {
     int32_t nnz_seg_max;      // CSR: nonzeros of the largest segment
     int32_t pad2;
     unsigned long long* prof; // [PROF_SLOTS] phase times of workgroup 0 (wall-clock ticks), or NULL
+    const uint32_t* bits;     // LAY_BITS: rows as bitsets [n][wpr]
+    int32_t wpr;
+    int32_t pad3;
 };
 
 // Residency of a workgroup's segment during one launch of the SMO loop:
 // STEP_GLOBAL    per-row state (f, status, active list) and row payload in HBM;
 // STEP_LDS_STATE per-row state in LDS, row payload streamed from HBM;
-// STEP_LDS_ALL   per-row state and row payload (dense rows or CSR column ids
-//                as u16, plus values unless all are 1.0) in LDS.
+// STEP_LDS_ALL   per-row state and row payload (dense rows, CSR column ids
+//                as u16 plus values unless all are 1.0, or bitset rows) in LDS.
 enum : int { STEP_GLOBAL = 0, STEP_LDS_STATE = 1, STEP_LDS_ALL = 2 };
 constexpr int PROF_SLOTS = 8;
 constexpr size_t STEP_LDS_BUDGET = 156 * 1024;

@@ -33,6 +33,25 @@ static size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
 StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, long long nnz_seg_max,
                       bool pattern_only, int max_mode) {
     StepLds p{};
+    if (lay == LAY_BITS) {
+        const int wpr = bits_wpr(d);
+        p.pair_bytes = sizeof(uint32_t) * 2 * (size_t)wpr;
+        p.meta_off = al16(p.pair_bytes);
+        p.pay_off = p.meta_off + al16(2 * sizeof(double) * (size_t)nseg_max + sizeof(int) * (size_t)nseg_max +
+                                      (size_t)nseg_max);
+        const size_t pay = sizeof(uint32_t) * (size_t)wpr * nseg_max;
+        if (max_mode >= STEP_LDS_ALL && p.pay_off + pay <= STEP_LDS_BUDGET) {
+            p.mode = STEP_LDS_ALL;
+            p.total = p.pay_off + pay;
+        } else if (max_mode >= STEP_LDS_STATE && p.pay_off <= STEP_LDS_BUDGET) {
+            p.mode = STEP_LDS_STATE;
+            p.total = p.pay_off;
+        } else {
+            p.mode = STEP_GLOBAL;
+            p.total = p.pair_bytes;
+        }
+        return p;
+    }
     if (lay == LAY_DENSE) p.pair_bytes = sizeof(float2) * (size_t)dpad;
     else if (lay == LAY_CSR_TABLE) p.pair_bytes = sizeof(float2) * (size_t)d + sizeof(int) * 2 * (size_t)max_row_nnz;
     else
@@ -64,7 +83,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     constexpr int BLOCK = STEP_BLOCK;
     constexpr int NW = BLOCK / 64;
     constexpr int NG = BLOCK / LPR;
-    constexpr bool CSR = LAY != LAY_DENSE;
+    constexpr bool BITS = LAY == LAY_BITS;
+    constexpr bool CSR = LAY == LAY_CSR_TABLE || LAY == LAY_CSR_SLOT;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_v[4 * NW];
     __shared__ int s_i[2 * NW];
@@ -82,6 +102,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
 
     // ---- LDS: the working pair first
     float2* pairv = reinterpret_cast<float2*>(smem);
+    uint32_t* pairb = reinterpret_cast<uint32_t*>(smem);   // LAY_BITS: pair rows' bitsets
     uint16_t* slot = nullptr;
     int* prev_cols = nullptr;
     if (LAY == LAY_CSR_TABLE) {
@@ -107,6 +128,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     int* L;           // active list: global ids (STEP_GLOBAL) or segment-local indices
     int* OFF = nullptr;
     float* XL = nullptr;
+    uint32_t* XB = nullptr;   // LAY_BITS rows in LDS
     uint16_t* COLL = nullptr;
     float* VALL = nullptr;
     if constexpr (MODE == STEP_GLOBAL) {
@@ -128,7 +150,13 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         if (CSR)
             for (int li = tid; li <= nseg; li += BLOCK) OFF[li] = A.row_ptr[seg0 + li] - gbase;
         if constexpr (MODE == STEP_LDS_ALL) {
-            if (CSR) {
+            if (BITS) {
+                XB = reinterpret_cast<uint32_t*>(smem + A.lds_pay_off);
+                const uint4* src = reinterpret_cast<const uint4*>(A.bits + (size_t)seg0 * A.wpr);
+                uint4* dst = reinterpret_cast<uint4*>(XB);
+                const int n4 = nseg * (A.wpr / 4);
+                for (int e = tid; e < n4; e += BLOCK) dst[e] = src[e];
+            } else if (CSR) {
                 const int nnz = A.row_ptr[seg0 + nseg] - gbase;
                 COLL = reinterpret_cast<uint16_t*>(smem + A.lds_pay_off);
                 VALL = reinterpret_cast<float*>(smem + A.lds_pay_off + ((sizeof(uint16_t) * (size_t)A.nnz_seg_max + 15) & ~(size_t)15));
@@ -209,6 +237,29 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     if (lane == 0) s_pair[0] = (double)expf(-(float)A.gamma * a);
                 }
             }
+        } else if constexpr (BITS) {
+            const int wpr = A.wpr;
+            for (int k = tid; k < 2 * wpr; k += BLOCK)
+                pairb[k] = k < wpr ? A.bits[(size_t)iu * wpr + k] : A.bits[(size_t)il * wpr + (k - wpr)];
+            __syncthreads();
+            if (wid == 0) {
+                int cu = 0, cl = 0, cd = 0;
+                for (int k = lane; k < wpr; k += 64) {
+                    cu += __popc(pairb[k]);
+                    cl += __popc(pairb[wpr + k]);
+                    cd += __popc(pairb[k] & pairb[wpr + k]);
+                }
+                cu = wave_sum(cu);
+                cl = wave_sum(cl);
+                cd = wave_sum(cd);
+                if (lane == 0) {
+                    KT d2 = (KT)cu + (KT)cl - (KT)2 * (KT)cd;
+                    if (d2 < (KT)0) d2 = (KT)0;
+                    s_pair[0] = (double)kexp((KT)(-(KT)A.gamma * d2));
+                    s_pair[1] = (double)cu;
+                    s_pair[2] = (double)cl;
+                }
+            }
         } else {
             int pu0, pu1, pl0, pl1;
             if (ext_u) { pu0 = (int)(unsigned)(ext_u & 0xffffffffull); pu1 = (int)(unsigned)(ext_u >> 32); }
@@ -286,7 +337,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         __syncthreads();
         const PairNew pn = pair_update(au, al, yu, yl, bu, bl, s_pair[0], C);
         const KT gam = (KT)A.gamma;
-        const KT nuu = CSR ? (KT)s_pair[1] : (KT)0, nll = CSR ? (KT)s_pair[2] : (KT)0;
+        const KT nuu = (CSR || BITS) ? (KT)s_pair[1] : (KT)0, nll = (CSR || BITS) ? (KT)s_pair[2] : (KT)0;
 
         bool do_shrink = false;
         if (A.H > 0) {
@@ -311,6 +362,24 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                 if constexpr (LAY == LAY_DENSE) {
                     const float* xr = (MODE == STEP_LDS_ALL) ? XL + (size_t)li * A.dpad : A.x + (size_t)i * A.dpad;
                     dense_dist<KT>(xr, pairv, A.dpad, du2, dl2);
+                } else if constexpr (BITS) {
+                    // one lane per row: popcounts of the row's bitset against the pair's
+                    const uint4* xr = reinterpret_cast<const uint4*>(
+                        (MODE == STEP_LDS_ALL) ? XB + (size_t)li * A.wpr : A.bits + (size_t)i * A.wpr);
+                    const uint4* pu = reinterpret_cast<const uint4*>(pairb);
+                    const uint4* pl = reinterpret_cast<const uint4*>(pairb + A.wpr);
+                    int nn = 0, su = 0, sl2 = 0;
+                    for (int w4 = 0; w4 < A.wpr / 4; ++w4) {
+                        const uint4 v = xr[w4], a = pu[w4], b = pl[w4];
+                        nn += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+                        su += __popc(v.x & a.x) + __popc(v.y & a.y) + __popc(v.z & a.z) + __popc(v.w & a.w);
+                        sl2 += __popc(v.x & b.x) + __popc(v.y & b.y) + __popc(v.z & b.z) + __popc(v.w & b.w);
+                    }
+                    work_nnz += (unsigned long long)nn;
+                    du2 = (KT)nn + nuu - (KT)2 * (KT)su;
+                    dl2 = (KT)nn + nll - (KT)2 * (KT)sl2;
+                    if (du2 < (KT)0) du2 = (KT)0;
+                    if (dl2 < (KT)0) dl2 = (KT)0;
                 } else {
                     int p0, p1;
                     if constexpr (MODE == STEP_GLOBAL) {
@@ -493,25 +562,41 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                 break;
             }
             lap(3);
-            if (do_shrink) {
-                const long long csum = wave_sum(rcnt);
-                if (lane == 0) s_wc[wid] = (int)csum;
-            }
-            // reduce (value, id) -- every thread ends with the winners -- and the record holding
-            // each winner publishes its payload (alpha, CSR extent)
+            // reduce (value, id) and the record holding each winner publishes its payload
+            // (alpha, CSR extent); with at most 64 records wave 0 holds them all
             const int myiu = riu, myil = ril;
-            block_reduce_sel_all<BLOCK>(rbu, riu, rbl, ril, s_v, s_i);
-            if (tid < G) {
-                if (myiu != IDX_NONE && myiu == riu) { s_sel[2] = rau; s_ext[0] = reu; }
-                if (myil != IDX_NONE && myil == ril) { s_sel[3] = ral; s_ext[1] = rel; }
-            }
-            if (tid == 0) {
-                s_sel[0] = rbu; s_sel[1] = rbl;
-                s_seli[0] = riu; s_seli[1] = ril;
+            if (G <= 64) {
+                if (wid == 0) {
+                    const long long csum = do_shrink ? wave_sum(rcnt) : 0;
+                    wave_reduce_sel(rbu, riu, rbl, ril);
+                    if (tid < G) {
+                        if (myiu != IDX_NONE && myiu == riu) { s_sel[2] = rau; s_ext[0] = reu; }
+                        if (myil != IDX_NONE && myil == ril) { s_sel[3] = ral; s_ext[1] = rel; }
+                    }
+                    if (tid == 0) {
+                        s_sel[0] = rbu; s_sel[1] = rbl;
+                        s_seli[0] = riu; s_seli[1] = ril;
+                        if (do_shrink) s_seli[2] = (int)csum;
+                    }
+                }
+            } else {
                 if (do_shrink) {
-                    long long c = 0;
-                    for (int w = 0; w < NW; ++w) c += s_wc[w];
-                    s_seli[2] = (int)c;
+                    const long long csum = wave_sum(rcnt);
+                    if (lane == 0) s_wc[wid] = (int)csum;
+                }
+                block_reduce_sel_all<BLOCK>(rbu, riu, rbl, ril, s_v, s_i);
+                if (tid < G) {
+                    if (myiu != IDX_NONE && myiu == riu) { s_sel[2] = rau; s_ext[0] = reu; }
+                    if (myil != IDX_NONE && myil == ril) { s_sel[3] = ral; s_ext[1] = rel; }
+                }
+                if (tid == 0) {
+                    s_sel[0] = rbu; s_sel[1] = rbl;
+                    s_seli[0] = riu; s_seli[1] = ril;
+                    if (do_shrink) {
+                        long long c = 0;
+                        for (int w = 0; w < NW; ++w) c += s_wc[w];
+                        s_seli[2] = (int)c;
+                    }
                 }
             }
         } else {
@@ -589,7 +674,7 @@ static const void* loop_fn() {
 
 template <int LAY, typename KT, int MODE>
 static const void* pick_lpr(int lpr) {
-    if constexpr (LAY == LAY_DENSE) {
+    if constexpr (LAY == LAY_DENSE || LAY == LAY_BITS) {
         return loop_fn<LAY, KT, 1, MODE>();
     } else {
         switch (lpr) {
@@ -613,10 +698,12 @@ static const void* pick_mode(int mode, int lpr) {
 static const void* pick(int lay, int kprec, int mode, int lpr) {
     if (kprec == SVM_KERNEL_FP64) {
         if (lay == LAY_DENSE) return pick_mode<LAY_DENSE, double>(mode, lpr);
+        if (lay == LAY_BITS) return pick_mode<LAY_BITS, double>(mode, lpr);
         if (lay == LAY_CSR_TABLE) return pick_mode<LAY_CSR_TABLE, double>(mode, lpr);
         return pick_mode<LAY_CSR_SLOT, double>(mode, lpr);
     }
     if (lay == LAY_DENSE) return pick_mode<LAY_DENSE, float>(mode, lpr);
+    if (lay == LAY_BITS) return pick_mode<LAY_BITS, float>(mode, lpr);
     if (lay == LAY_CSR_TABLE) return pick_mode<LAY_CSR_TABLE, float>(mode, lpr);
     return pick_mode<LAY_CSR_SLOT, float>(mode, lpr);
 }
