@@ -196,42 +196,49 @@ DEV PairNew pair_update(double au, double al, int yu, int yl, double bu, double 
 // by direct difference in the order k = 0..dpad-1 (padding contributes 0).
 template <typename KT>
 DEV void dense_dist(const float* __restrict__ xr, const float2* __restrict__ pair, int dpad, KT& su, KT& sl) {
+    // the row's loads are issued in blocks of DB float4 before any of them is used, so a row
+    // read from HBM costs about one memory latency per block instead of one per float4
+    constexpr int DB = 8;
     const float4* x4 = reinterpret_cast<const float4*>(xr);
     const float4* p4 = reinterpret_cast<const float4*>(pair);
-    if constexpr (std::is_same<KT, double>::value) {
+    const int n4 = dpad / 4;
+    KT a = 0, b = 0;
+    for (int k0 = 0; k0 < n4; k0 += DB) {
+        float4 v[DB];
+#pragma unroll
+        for (int j = 0; j < DB; ++j)
+            if (k0 + j < n4) v[j] = x4[k0 + j];
+#pragma unroll
+        for (int j = 0; j < DB; ++j) {
+            if (k0 + j < n4) {
+                const float4 q0 = p4[2 * (k0 + j)], q1 = p4[2 * (k0 + j) + 1];   // (u0 l0 u1 l1) (u2 l2 u3 l3)
+                if constexpr (std::is_same<KT, double>::value) {
 #pragma clang fp contract(off)
-        double a = 0.0, b = 0.0;
-        for (int k4 = 0; k4 < dpad / 4; ++k4) {
-            float4 v = x4[k4];
-            float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];   // (u0 l0 u1 l1) (u2 l2 u3 l3)
-            double t;
-            t = (double)v.x - (double)q0.x; a = a + t * t;
-            t = (double)v.x - (double)q0.y; b = b + t * t;
-            t = (double)v.y - (double)q0.z; a = a + t * t;
-            t = (double)v.y - (double)q0.w; b = b + t * t;
-            t = (double)v.z - (double)q1.x; a = a + t * t;
-            t = (double)v.z - (double)q1.y; b = b + t * t;
-            t = (double)v.w - (double)q1.z; a = a + t * t;
-            t = (double)v.w - (double)q1.w; b = b + t * t;
+                    double t;
+                    t = (double)v[j].x - (double)q0.x; a = a + t * t;
+                    t = (double)v[j].x - (double)q0.y; b = b + t * t;
+                    t = (double)v[j].y - (double)q0.z; a = a + t * t;
+                    t = (double)v[j].y - (double)q0.w; b = b + t * t;
+                    t = (double)v[j].z - (double)q1.x; a = a + t * t;
+                    t = (double)v[j].z - (double)q1.y; b = b + t * t;
+                    t = (double)v[j].w - (double)q1.z; a = a + t * t;
+                    t = (double)v[j].w - (double)q1.w; b = b + t * t;
+                } else {
+                    float t;
+                    t = v[j].x - q0.x; a = fmaf(t, t, a);
+                    t = v[j].x - q0.y; b = fmaf(t, t, b);
+                    t = v[j].y - q0.z; a = fmaf(t, t, a);
+                    t = v[j].y - q0.w; b = fmaf(t, t, b);
+                    t = v[j].z - q1.x; a = fmaf(t, t, a);
+                    t = v[j].z - q1.y; b = fmaf(t, t, b);
+                    t = v[j].w - q1.z; a = fmaf(t, t, a);
+                    t = v[j].w - q1.w; b = fmaf(t, t, b);
+                }
+            }
         }
-        su = a; sl = b;
-    } else {
-        float a = 0.f, b = 0.f;
-        for (int k4 = 0; k4 < dpad / 4; ++k4) {
-            float4 v = x4[k4];
-            float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
-            float t;
-            t = v.x - q0.x; a = fmaf(t, t, a);
-            t = v.x - q0.y; b = fmaf(t, t, b);
-            t = v.y - q0.z; a = fmaf(t, t, a);
-            t = v.y - q0.w; b = fmaf(t, t, b);
-            t = v.z - q1.x; a = fmaf(t, t, a);
-            t = v.z - q1.y; b = fmaf(t, t, b);
-            t = v.w - q1.z; a = fmaf(t, t, a);
-            t = v.w - q1.w; b = fmaf(t, t, b);
-        }
-        su = a; sl = b;
     }
+    su = a;
+    sl = b;
 }
 
 

@@ -469,7 +469,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         // workgroup writes, so they travel in the records instead of being re-read later
         double cau = 0.0, cal = 0.0;
         unsigned long long ceu = 0, cel = 0;
-        if (tid == 0) {
+        if (wid == 0) {   // every lane of wave 0: the record's words are stored one per lane
             if (ciu != IDX_NONE) {
                 if constexpr (MODE == STEP_GLOBAL) cau = ld_agent(A.alpha + ciu);
                 else cau = AL[ciu - seg0];
@@ -497,27 +497,30 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
             const int par = (int)(iter & 1);
             const unsigned tg = (unsigned)(iter + 1);
             const unsigned long long TAG = (unsigned long long)tg << 32;
-            if (tid == 0) {
-                unsigned long long* w = A.rec[par * G + blk].w;
+            if (wid == 0 && lane < REC_WORDS) {   // word `lane` of the record, one store per lane
                 const unsigned long long bub = (unsigned long long)__double_as_longlong(cbu);
                 const unsigned long long blb = (unsigned long long)__double_as_longlong(cbl);
                 const unsigned long long aub = (unsigned long long)__double_as_longlong(cau);
                 const unsigned long long alb = (unsigned long long)__double_as_longlong(cal);
-                st_agent(w + 0, TAG | (bub & 0xffffffffull));
-                st_agent(w + 1, TAG | (bub >> 32));
-                st_agent(w + 2, TAG | (blb & 0xffffffffull));
-                st_agent(w + 3, TAG | (blb >> 32));
-                st_agent(w + 4, TAG | (unsigned)ciu);
-                st_agent(w + 5, TAG | (unsigned)cil);
-                st_agent(w + 6, TAG | (unsigned)nrows);
-                st_agent(w + 7, TAG | (aub & 0xffffffffull));
-                st_agent(w + 8, TAG | (aub >> 32));
-                st_agent(w + 9, TAG | (alb & 0xffffffffull));
-                st_agent(w + 10, TAG | (alb >> 32));
-                st_agent(w + 11, TAG | (ceu & 0xffffffffull));
-                st_agent(w + 12, TAG | (ceu >> 32));
-                st_agent(w + 13, TAG | (cel & 0xffffffffull));
-                st_agent(w + 14, TAG | (cel >> 32));
+                unsigned long long x;
+                switch (lane) {
+                    case 0: x = bub; break;
+                    case 1: x = bub >> 32; break;
+                    case 2: x = blb; break;
+                    case 3: x = blb >> 32; break;
+                    case 4: x = (unsigned)ciu; break;
+                    case 5: x = (unsigned)cil; break;
+                    case 6: x = (unsigned)nrows; break;
+                    case 7: x = aub; break;
+                    case 8: x = aub >> 32; break;
+                    case 9: x = alb; break;
+                    case 10: x = alb >> 32; break;
+                    case 11: x = ceu; break;
+                    case 12: x = ceu >> 32; break;
+                    case 13: x = cel; break;
+                    default: x = cel >> 32; break;
+                }
+                st_agent(A.rec[par * G + blk].w + lane, TAG | (x & 0xffffffffull));
             }
             lap(2);
             double rbu = INFINITY, rbl = -INFINITY, rau = 0.0, ral = 0.0;
@@ -580,21 +583,34 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     }
                 }
             } else {
-                if (do_shrink) {
-                    const long long csum = wave_sum(rcnt);
-                    if (lane == 0) s_wc[wid] = (int)csum;
+                // waves 0 .. NR-1 hold 64 records each: reduce within them, then combine NR values
+                const int NR = (G + 63) / 64;
+                if (wid < NR) {
+                    const long long csum = do_shrink ? wave_sum(rcnt) : 0;
+                    wave_reduce_sel(rbu, riu, rbl, ril);
+                    if (lane == 0) {
+                        s_v[wid] = rbu; s_i[wid] = riu;
+                        s_v[NW + wid] = rbl; s_i[NW + wid] = ril;
+                        s_wc[wid] = (int)csum;
+                    }
                 }
-                block_reduce_sel_all<BLOCK>(rbu, riu, rbl, ril, s_v, s_i);
+                __syncthreads();
+                double xbu = s_v[0], xbl = s_v[NW];
+                int xiu = s_i[0], xil = s_i[NW];
+                for (int w = 1; w < NR; ++w) {
+                    if (better_up(s_v[w], s_i[w], xbu, xiu)) { xbu = s_v[w]; xiu = s_i[w]; }
+                    if (better_low(s_v[NW + w], s_i[NW + w], xbl, xil)) { xbl = s_v[NW + w]; xil = s_i[NW + w]; }
+                }
                 if (tid < G) {
-                    if (myiu != IDX_NONE && myiu == riu) { s_sel[2] = rau; s_ext[0] = reu; }
-                    if (myil != IDX_NONE && myil == ril) { s_sel[3] = ral; s_ext[1] = rel; }
+                    if (myiu != IDX_NONE && myiu == xiu) { s_sel[2] = rau; s_ext[0] = reu; }
+                    if (myil != IDX_NONE && myil == xil) { s_sel[3] = ral; s_ext[1] = rel; }
                 }
                 if (tid == 0) {
-                    s_sel[0] = rbu; s_sel[1] = rbl;
-                    s_seli[0] = riu; s_seli[1] = ril;
+                    s_sel[0] = xbu; s_sel[1] = xbl;
+                    s_seli[0] = xiu; s_seli[1] = xil;
                     if (do_shrink) {
                         long long c = 0;
-                        for (int w = 0; w < NW; ++w) c += s_wc[w];
+                        for (int w = 0; w < NR; ++w) c += s_wc[w];
                         s_seli[2] = (int)c;
                     }
                 }
