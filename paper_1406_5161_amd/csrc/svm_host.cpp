@@ -222,7 +222,13 @@ struct Solver {
         const int W = lay == LAY_DENSE ? dpad : d;
         int R = (int)std::min<size_t>(16, (96 * 1024) / (sizeof(float) * (size_t)W));
         int blocks;
-        if (kernel_sum_uses_mfma(a.lay, dpad, q->kernel_precision)) {
+        if (lay == LAY_BITS) {
+            a.lay = LAY_BITS;
+            a.abits = a.bbits = bits;
+            a.wpr = bits_wpr(d);
+            a.rows_per_block = 16;
+            blocks = (nrows + 15) / 16;
+        } else if (kernel_sum_uses_mfma(a.lay, dpad, q->kernel_precision)) {
             a.rows_per_block = KSUM_MFMA_ROWS;
             blocks = (nrows + KSUM_MFMA_ROWS - 1) / KSUM_MFMA_ROWS;
         } else if (R < 1) {

@@ -120,7 +120,7 @@ StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, l
 
 // Kernel sums: out[a] = sum_b coef[b] * K(A_a, B_b) + bias_a, bias_a = -y_a or -beta.
 struct SumArgs {
-    int32_t lay;              // LAY_DENSE or LAY_CSR_TABLE (A and B share the layout)
+    int32_t lay;              // LAY_DENSE, LAY_CSR_TABLE, LAY_CSR_SLOT or LAY_BITS (A and B share it)
     int32_t d, dpad;
     // A side
     const float* ax;
@@ -141,6 +141,11 @@ struct SumArgs {
     double* part;
     double gamma;
     int32_t rows_per_block;   // A rows held in LDS per workgroup
+    // LAY_BITS: both sides as bitsets of wpr words per row
+    const uint32_t* abits;
+    const uint32_t* bbits;
+    int32_t wpr;
+    int32_t pad;
 };
 
 // ---- launch wrappers (device code in svm_kernels.hip)

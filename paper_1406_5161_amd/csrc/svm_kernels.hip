@@ -589,12 +589,90 @@ __global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_mfma_kernel(SumArgs A) {
     }
 }
 
+// Binary rows as bitsets (LAY_BITS): a workgroup holds R = 16 A rows' bitsets in LDS and
+// sweeps its split of the B list, one B row per thread and step; the squared distance is
+// |a| + |b| - 2 |a & b| from popcounts (exact integers), then exp and FP64 sums as above.
+constexpr int BITS_R = 16;
+
+template <typename KT>
+__global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_bits_kernel(SumArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double s_red[SUM_BLOCK / 64][BITS_R];
+    __shared__ int s_na[BITS_R];
+    uint32_t* at = reinterpret_cast<uint32_t*>(smem);   // [BITS_R][wpr]
+    const int wpr = A.wpr;
+    const int r0 = blockIdx.x * BITS_R;
+    const int nr = min(BITS_R, A.na - r0);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int e = tid; e < BITS_R * wpr; e += SUM_BLOCK) {
+        const int r = e / wpr, k = e % wpr;
+        at[e] = r < nr ? A.abits[(size_t)(A.alist ? A.alist[r0 + r] : r0 + r) * wpr + k] : 0u;
+    }
+    __syncthreads();
+    if (tid < BITS_R) {
+        int c = 0;
+        for (int k = 0; k < wpr; ++k) c += __popc(at[tid * wpr + k]);
+        s_na[tid] = c;
+    }
+    __syncthreads();
+    double acc[BITS_R];
+#pragma unroll
+    for (int r = 0; r < BITS_R; ++r) acc[r] = 0.0;
+    const KT gam = (KT)A.gamma;
+    const int per = (A.nb + A.nsplit - 1) / A.nsplit;
+    const int b0 = blockIdx.y * per, b1 = min(A.nb, b0 + per);
+    for (int jb = b0 + tid; jb < b1; jb += SUM_BLOCK) {
+        const int j = A.blist[jb];
+        const double cj = A.coef[jb];
+        const uint4* xb = reinterpret_cast<const uint4*>(A.bbits + (size_t)j * wpr);
+        int nb = 0, dot[BITS_R];
+#pragma unroll
+        for (int r = 0; r < BITS_R; ++r) dot[r] = 0;
+        for (int w4 = 0; w4 < wpr / 4; ++w4) {
+            const uint4 v = xb[w4];
+            nb += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+#pragma unroll
+            for (int r = 0; r < BITS_R; ++r) {
+                const uint4 t = reinterpret_cast<const uint4*>(at + r * wpr)[w4];
+                dot[r] += __popc(v.x & t.x) + __popc(v.y & t.y) + __popc(v.z & t.z) + __popc(v.w & t.w);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < BITS_R; ++r) {
+            if (r < nr) {
+                KT d2 = (KT)s_na[r] + (KT)nb - (KT)2 * (KT)dot[r];
+                if (d2 < (KT)0) d2 = (KT)0;
+                acc[r] += cj * (double)kexp(-gam * d2);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < BITS_R; ++r) {
+        const double v = wave_sum(acc[r]);
+        if (lane == 0) s_red[wid][r] = v;
+    }
+    __syncthreads();
+    if (tid < nr) {
+        double v = 0.0;
+        for (int w = 0; w < SUM_BLOCK / 64; ++w) v += s_red[w][tid];
+        A.part[(size_t)blockIdx.y * A.na + r0 + tid] = v;
+    }
+}
+
 bool kernel_sum_uses_mfma(int lay, int dpad, int kprec) {
     return lay == LAY_DENSE && kprec == SVM_KERNEL_FP32 && dpad <= MF_MAX_DPAD;
 }
 
 hipError_t launch_kernel_sum(const SumArgs& a, int kprec, hipStream_t s) {
     if (a.na <= 0) return hipSuccess;
+    if (a.lay == LAY_BITS) {
+        const size_t lds = sizeof(uint32_t) * BITS_R * (size_t)a.wpr;
+        dim3 grid((a.na + BITS_R - 1) / BITS_R, a.nsplit);
+        SumArgs c = a;
+        if (kprec == SVM_KERNEL_FP64) kernel_sum_bits_kernel<double><<<grid, SUM_BLOCK, lds, s>>>(c);
+        else kernel_sum_bits_kernel<float><<<grid, SUM_BLOCK, lds, s>>>(c);
+        return hipGetLastError();
+    }
     if (kernel_sum_uses_mfma(a.lay, a.dpad, kprec)) {
         const size_t lds = sizeof(float) * 2 * MF_T * (size_t)(a.dpad + 1);
         dim3 grid((a.na + MF_T - 1) / MF_T, a.nsplit);
