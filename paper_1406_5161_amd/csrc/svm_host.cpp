@@ -235,7 +235,8 @@ struct Solver {
             // CSR too wide to stage rows in LDS: slot-map densification, one row per workgroup
             a.lay = LAY_CSR_SLOT;
             a.rows_per_block = max_row_nnz;
-            blocks = std::min(nrows, 2048);
+            a.slot_rows = slot_rows_for(d, max_row_nnz);
+            blocks = std::min((nrows + a.slot_rows - 1) / a.slot_rows, 2048);
         } else {
             a.rows_per_block = R;
             blocks = (nrows + R - 1) / R;
@@ -664,7 +665,8 @@ int svm_decision(const svm_problem_t* train, const double* alpha, double beta, d
         for (int i = 0; i < nq; ++i) mx = std::max(mx, rp[i + 1] - rp[i]);
         a.lay = LAY_CSR_SLOT;
         a.rows_per_block = mx;
-        blocks = std::min(nq, 2048);
+        a.slot_rows = slot_rows_for(d, mx);
+        blocks = std::min((nq + a.slot_rows - 1) / a.slot_rows, 2048);
     } else {
         a.rows_per_block = R;
         blocks = (nq + R - 1) / R;

@@ -145,8 +145,11 @@ struct SumArgs {
     const uint32_t* abits;
     const uint32_t* bbits;
     int32_t wpr;
-    int32_t pad;
+    int32_t slot_rows;        // LAY_CSR_SLOT: A rows per group (slot_rows_for)
 };
+// A rows the wide-CSR kernel sum groups per pass for the longest row max_nnz and d columns:
+// the most (at most 8) whose column table fits the LDS next to the slot map.
+int slot_rows_for(int d, int max_nnz);
 
 // ---- launch wrappers (device code in svm_kernels.hip)
 hipError_t launch_validate(int n, int d, int lay, const float* x, int64_t ldx, int feature_major,

@@ -320,6 +320,7 @@ hipError_t launch_compact(int n, int pred, const uint8_t* mask, const double* al
 // split go to part[split][a]; launch_finish_sum adds the splits in order.
 constexpr int SUM_BLOCK = 256;
 constexpr int SUM_RMAX = 16;
+constexpr int SLOT_R_MAX = 8;
 
 template <int LAY, typename KT>
 __global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_kernel(SumArgs A) {
@@ -443,66 +444,101 @@ __global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_kernel(SumArgs A) {
     }
 }
 
-// Large-d CSR: one A row at a time per workgroup, densified through a u16 slot
-// map over the d columns (zeroed once, cleared sparsely after each row).
+// Large-d CSR: a few A rows at a time per workgroup, densified through a u16 slot map over
+// the d columns (zeroed once, cleared sparsely after each group).
 template <typename KT>
 __global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_slot_kernel(SumArgs A) {
+    // R = A.slot_rows target rows at a time: slot[c] numbers the columns of their union
+    // (1-based; 0 = in none of them) and tab[slot][r] holds row r's value there, so one pass
+    // over a support vector's nonzeros serves all R rows
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double s_red[SUM_BLOCK / 64];
-    __shared__ double s_na;
-    float* av = reinterpret_cast<float*>(smem);                       // [1 + max_row_nnz]
-    uint16_t* slot = reinterpret_cast<uint16_t*>(smem + ((sizeof(float) * (size_t)(1 + A.rows_per_block) + 15) & ~(size_t)15));
+    __shared__ double s_red[SUM_BLOCK / 64][SLOT_R_MAX];
+    __shared__ double s_na[SLOT_R_MAX];
+    __shared__ int s_u;
+    const int R = A.slot_rows;
+    uint16_t* slot = reinterpret_cast<uint16_t*>(smem);
+    float* tab = reinterpret_cast<float*>(smem + ((sizeof(uint16_t) * (size_t)A.d + 15) & ~(size_t)15));
+    const int tab_rows = 1 + R * A.rows_per_block;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     for (int k = tid; k < A.d; k += SUM_BLOCK) slot[k] = 0;
-    if (tid == 0) av[0] = 0.f;
+    for (int e = tid; e < tab_rows * R; e += SUM_BLOCK) tab[e] = 0.f;
     __syncthreads();
     const KT gam = (KT)A.gamma;
     const int per = (A.nb + A.nsplit - 1) / A.nsplit;
     const int b0 = blockIdx.y * per, b1 = min(A.nb, b0 + per);
-    for (int r = blockIdx.x; r < A.na; r += gridDim.x) {
-        const int a = A.alist ? A.alist[r] : r;
-        const int p0 = A.arp[a], p1 = A.arp[a + 1];
-        KT nn = 0;
-        for (int p = p0 + tid; p < p1; p += SUM_BLOCK) {
-            slot[A.acol[p]] = (uint16_t)(1 + p - p0);
-            const float v = A.aval[p];
-            av[1 + p - p0] = v;
-            nn += (KT)v * (KT)v;
-        }
-        nn = wave_sum(nn);
-        if (lane == 0) s_red[wid] = (double)nn;
-        __syncthreads();
+    const int ngroups = (A.na + R - 1) / R;
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int r0 = grp * R, nr = min(R, A.na - r0);
+        // union of the group's columns: one thread per row claims slots in row order
         if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < SUM_BLOCK / 64; ++w) t += s_red[w];
-            s_na = t;
+            int u = 0;
+            for (int r = 0; r < nr; ++r) {
+                const int a = A.alist ? A.alist[r0 + r] : r0 + r;
+                for (int p = A.arp[a]; p < A.arp[a + 1]; ++p) {
+                    const int c = A.acol[p];
+                    int sl = slot[c];
+                    if (!sl) { sl = ++u; slot[c] = (uint16_t)sl; }
+                    tab[sl * R + r] = A.aval[p];
+                }
+            }
+            s_u = u;
         }
         __syncthreads();
-        const KT na = (KT)s_na;
-        double acc = 0.0;
+        if (tid < nr) {
+            const int a = A.alist ? A.alist[r0 + tid] : r0 + tid;
+            KT nn = 0;
+            for (int p = A.arp[a]; p < A.arp[a + 1]; ++p) {
+                const KT v = (KT)A.aval[p];
+                nn += v * v;
+            }
+            s_na[tid] = (double)nn;
+        }
+        __syncthreads();
+        double acc[SLOT_R_MAX];
+#pragma unroll
+        for (int r = 0; r < SLOT_R_MAX; ++r) acc[r] = 0.0;
         for (int jb = b0 + tid; jb < b1; jb += SUM_BLOCK) {
             const int j = A.blist[jb];
             const int q0 = A.brp[j], q1 = A.brp[j + 1];
-            KT nb = 0, dot = 0;
+            KT nb = 0, dot[SLOT_R_MAX];
+#pragma unroll
+            for (int r = 0; r < SLOT_R_MAX; ++r) dot[r] = 0;
             for (int q = q0; q < q1; ++q) {
                 const KT v = (KT)A.bval[q];
                 nb += v * v;
-                dot += v * (KT)av[slot[A.bcol[q]]];
+                const float* t = tab + (int)slot[A.bcol[q]] * R;
+#pragma unroll
+                for (int r = 0; r < SLOT_R_MAX; ++r)
+                    if (r < R) dot[r] += v * (KT)t[r];
             }
-            KT d2 = na + nb - (KT)2 * dot;
-            if (d2 < (KT)0) d2 = (KT)0;
-            acc += A.coef[jb] * (double)kexp(-gam * d2);
+#pragma unroll
+            for (int r = 0; r < SLOT_R_MAX; ++r) {
+                if (r < nr) {
+                    KT d2 = (KT)s_na[r] + nb - (KT)2 * dot[r];
+                    if (d2 < (KT)0) d2 = (KT)0;
+                    acc[r] += A.coef[jb] * (double)kexp(-gam * d2);
+                }
+            }
         }
-        acc = wave_sum(acc);
+#pragma unroll
+        for (int r = 0; r < SLOT_R_MAX; ++r) {
+            const double v = wave_sum(acc[r]);
+            if (lane == 0) s_red[wid][r] = v;
+        }
         __syncthreads();
-        if (lane == 0) s_red[wid] = acc;
-        __syncthreads();
-        if (tid == 0) {
+        if (tid < nr) {
             double t = 0.0;
-            for (int w = 0; w < SUM_BLOCK / 64; ++w) t += s_red[w];
-            A.part[(size_t)blockIdx.y * A.na + r] = t;
+            for (int w = 0; w < SUM_BLOCK / 64; ++w) t += s_red[w][tid];
+            A.part[(size_t)blockIdx.y * A.na + r0 + tid] = t;
         }
-        for (int p = p0 + tid; p < p1; p += SUM_BLOCK) slot[A.acol[p]] = 0;
+        // clear the group's slots and table rows for the next group
+        if (tid == 0) {
+            for (int r = 0; r < nr; ++r) {
+                const int a = A.alist ? A.alist[r0 + r] : r0 + r;
+                for (int p = A.arp[a]; p < A.arp[a + 1]; ++p) slot[A.acol[p]] = 0;
+            }
+        }
+        for (int e = tid; e < (1 + s_u) * R; e += SUM_BLOCK) tab[e] = 0.f;
         __syncthreads();
     }
 }
@@ -659,6 +695,14 @@ __global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_bits_kernel(SumArgs A) {
     }
 }
 
+int slot_rows_for(int d, int max_nnz) {
+    const size_t budget = 150 * 1024;
+    const size_t base = (sizeof(uint16_t) * (size_t)d + 15) & ~(size_t)15;
+    for (int r = SLOT_R_MAX; r > 1; r /= 2)
+        if (base + sizeof(float) * (size_t)(1 + r * max_nnz) * r <= budget) return r;
+    return 1;
+}
+
 bool kernel_sum_uses_mfma(int lay, int dpad, int kprec) {
     return lay == LAY_DENSE && kprec == SVM_KERNEL_FP32 && dpad <= MF_MAX_DPAD;
 }
@@ -683,10 +727,10 @@ hipError_t launch_kernel_sum(const SumArgs& a, int kprec, hipStream_t s) {
         return hipGetLastError();
     }
     if (a.lay == LAY_CSR_SLOT) {
-        // rows_per_block carries the longest A row here
-        const size_t lds = ((sizeof(float) * (size_t)(1 + a.rows_per_block) + 15) & ~(size_t)15) +
-                           sizeof(uint16_t) * (size_t)a.d;
-        dim3 grid(std::min(a.na, 2048), a.nsplit);
+        // rows_per_block carries the longest A row here, slot_rows the rows per group
+        const size_t lds = ((sizeof(uint16_t) * (size_t)a.d + 15) & ~(size_t)15) +
+                           sizeof(float) * (size_t)(1 + a.slot_rows * a.rows_per_block) * a.slot_rows;
+        dim3 grid(std::min((a.na + a.slot_rows - 1) / a.slot_rows, 2048), a.nsplit);
         SumArgs c = a;
         if (kprec == SVM_KERNEL_FP64) {
             (void)hipFuncSetAttribute((const void*)kernel_sum_slot_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

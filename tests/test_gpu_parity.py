@@ -296,13 +296,15 @@ def test_fp32_tight_eps_matches_oracle_decisions(S, case):
 
 # ------------------------------------------------------------------ decision kernel alone
 
-@pytest.mark.parametrize("layout", ["dense", "csr"])
+@pytest.mark.parametrize("layout", ["dense", "csr", "csr_wide"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_decision_matches_oracle_for_any_alpha(S, layout, prec):
     if layout == "dense":
         cfg = g.config1(n=1700, d=33)
-    else:
+    elif layout == "csr":
         cfg = sub(g.config2(), 1700)
+    else:   # d = 47,000: slot-map kernel sums over groups of query rows, ragged last group
+        cfg = sub(g.config3(n=20_000), 1700)
     rng = np.random.default_rng(11)
     alpha = np.where(rng.random(cfg.data.n) < 0.4, rng.uniform(0, cfg.C, cfg.data.n), 0.0)
     q = cfg.queries.subset(np.arange(777))
