@@ -77,7 +77,10 @@ def recon_summary(results, data):
     (2 * dpad per pair) against the FP32 matrix peak."""
     ms = sum(r.ms_ksum for r in results)
     pairs = sum(r.recon_pairs for r in results)
-    rec = {"kernel": "kernel_sum_mfma_kernel" if results[-1].ksum_mfma else "kernel_sum_kernel",
+    kern = ("kernel_sum_mfma_kernel" if results[-1].ksum_mfma
+            else "kernel_sum_bits_kernel" if data.layout == "csr" and results[-1].pattern_only and data.d <= 1024
+            else "kernel_sum_slot_kernel" if data.layout == "csr" and data.d > 12288 else "kernel_sum_kernel")
+    rec = {"kernel": kern,
            "ms_per_solve": ms / len(results), "pairs_per_solve": pairs / len(results),
            "pairs_per_s": pairs / (ms * 1e-3) if ms > 0 else None}
     if results[-1].ksum_mfma:
