@@ -112,42 +112,56 @@ DEV void rows_dist(bool dense, int dpad, const float* xb, const OT* off, const C
                    bool pattern, const float2* pairv, const int* ri, const bool* vv, int gl, int lpr, KT nuu,
                    KT nll, KT* du2, KT* dl2) {
     if (dense) {
+        // DU k-steps of every row are loaded before any is used: a chunk read from HBM costs
+        // one memory latency per DU k-steps
+        constexpr int DU = 2;
         const float4* p4 = reinterpret_cast<const float4*>(pairv);
+        const int n4 = dpad / 4;
         KT a[RPT], b[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) { a[r] = 0; b[r] = 0; }
-        for (int k4 = gl; k4 < dpad / 4; k4 += lpr) {
-            const float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
-            float4 v[RPT];
+        for (int k0 = gl; k0 < n4; k0 += DU * lpr) {
+            float4 v[DU][RPT];
 #pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                v[r] = vv[r] ? reinterpret_cast<const float4*>(xb + (size_t)ri[r] * dpad)[k4]
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int u = 0; u < DU; ++u) {
+                const int k4 = k0 + u * lpr;
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                if constexpr (std::is_same<KT, double>::value) {
+                for (int r = 0; r < RPT; ++r)
+                    v[u][r] = (vv[r] && k4 < n4) ? reinterpret_cast<const float4*>(xb + (size_t)ri[r] * dpad)[k4]
+                                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < DU; ++u) {
+                const int k4 = k0 + u * lpr;
+                if (k4 >= n4) break;
+                const float4 q0 = p4[2 * k4], q1 = p4[2 * k4 + 1];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const float4 w = v[u][r];
+                    if constexpr (std::is_same<KT, double>::value) {
 #pragma clang fp contract(off)
-                    double t, x = a[r], y = b[r];
-                    t = (double)v[r].x - (double)q0.x; x = x + t * t;
-                    t = (double)v[r].x - (double)q0.y; y = y + t * t;
-                    t = (double)v[r].y - (double)q0.z; x = x + t * t;
-                    t = (double)v[r].y - (double)q0.w; y = y + t * t;
-                    t = (double)v[r].z - (double)q1.x; x = x + t * t;
-                    t = (double)v[r].z - (double)q1.y; y = y + t * t;
-                    t = (double)v[r].w - (double)q1.z; x = x + t * t;
-                    t = (double)v[r].w - (double)q1.w; y = y + t * t;
-                    a[r] = x; b[r] = y;
-                } else {
-                    float t, x = a[r], y = b[r];
-                    t = v[r].x - q0.x; x = fmaf(t, t, x);
-                    t = v[r].x - q0.y; y = fmaf(t, t, y);
-                    t = v[r].y - q0.z; x = fmaf(t, t, x);
-                    t = v[r].y - q0.w; y = fmaf(t, t, y);
-                    t = v[r].z - q1.x; x = fmaf(t, t, x);
-                    t = v[r].z - q1.y; y = fmaf(t, t, y);
-                    t = v[r].w - q1.z; x = fmaf(t, t, x);
-                    t = v[r].w - q1.w; y = fmaf(t, t, y);
-                    a[r] = x; b[r] = y;
+                        double t, x = a[r], y = b[r];
+                        t = (double)w.x - (double)q0.x; x = x + t * t;
+                        t = (double)w.x - (double)q0.y; y = y + t * t;
+                        t = (double)w.y - (double)q0.z; x = x + t * t;
+                        t = (double)w.y - (double)q0.w; y = y + t * t;
+                        t = (double)w.z - (double)q1.x; x = x + t * t;
+                        t = (double)w.z - (double)q1.y; y = y + t * t;
+                        t = (double)w.w - (double)q1.z; x = x + t * t;
+                        t = (double)w.w - (double)q1.w; y = y + t * t;
+                        a[r] = x; b[r] = y;
+                    } else {
+                        float t, x = a[r], y = b[r];
+                        t = w.x - q0.x; x = fmaf(t, t, x);
+                        t = w.x - q0.y; y = fmaf(t, t, y);
+                        t = w.y - q0.z; x = fmaf(t, t, x);
+                        t = w.y - q0.w; y = fmaf(t, t, y);
+                        t = w.z - q1.x; x = fmaf(t, t, x);
+                        t = w.z - q1.y; y = fmaf(t, t, y);
+                        t = w.w - q1.z; x = fmaf(t, t, x);
+                        t = w.w - q1.w; y = fmaf(t, t, y);
+                        a[r] = x; b[r] = y;
+                    }
                 }
             }
         }
@@ -291,11 +305,18 @@ DEV bool team_read(const unsigned long long* trec, int B, unsigned seq, unsigned
     return __all(ok);
 }
 
+// Called by every lane of wave 0 with the same v: lane k < REC_WORDS stores word k, so the
+// record leaves in one store instruction.
 DEV void team_write(unsigned long long* trec, int B, int rank, unsigned seq, const unsigned* v) {
-    unsigned long long* w = trec + ((size_t)(seq & 1) * B + rank) * 16;
-    const unsigned long long TAG = (unsigned long long)seq << 32;
+    const int lane = threadIdx.x & 63;
+    unsigned x = v[0];
 #pragma unroll
-    for (int k = 0; k < REC_WORDS; ++k) st_agent(w + k, TAG | v[k]);
+    for (int k = 1; k < REC_WORDS; ++k)
+        if (lane == k) x = v[k];
+    if (lane < REC_WORDS) {
+        unsigned long long* w = trec + ((size_t)(seq & 1) * B + rank) * 16;
+        st_agent(w + lane, ((unsigned long long)seq << 32) | x);
+    }
 }
 
 DEV void pack_d(unsigned* v, int k, double x) {
@@ -307,7 +328,8 @@ DEV double unpack_d(const unsigned* v, int k) {
     return __longlong_as_double((long long)(((unsigned long long)v[k + 1] << 32) | v[k]));
 }
 
-// Merge the members' candidates (called by every thread; thread 0 holds this member's values).
+// Merge the members' candidates (called by every thread; every lane of wave 0 holds this
+// member's values).
 DEV TeamSel team_select(const BatchDesc& P, int rank, unsigned seq, double bu, int iu, double au, double bl,
                         int il, double al, long long cnt, BatchShared& sh) {
     const int tid = threadIdx.x;
@@ -318,7 +340,7 @@ DEV TeamSel team_select(const BatchDesc& P, int rank, unsigned seq, double bu, i
             sh.tseli[0] = iu; sh.tseli[1] = il; sh.tcnt = cnt; sh.tok = 1;
         }
     } else {
-        if (tid == 0) {
+        if (tid < 64) {
             unsigned v[REC_WORDS];
             pack_d(v, 0, bu); pack_d(v, 2, bl); pack_d(v, 4, au); pack_d(v, 6, al);
             v[8] = (unsigned)iu; v[9] = (unsigned)il;
@@ -361,7 +383,8 @@ DEV TeamSel team_select(const BatchDesc& P, int rank, unsigned seq, double bu, i
     return r;
 }
 
-// Sum 6 doubles over the team (thread 0 holds this member's values); every thread gets the totals.
+// Sum 6 doubles over the team (every lane of wave 0 holds this member's values; thread 0 is
+// enough for a team of one); every thread gets the totals.
 // With fence = true the exchange also publishes every global write made before it (alpha of the
 // pair rows) to the other members.
 DEV bool team_sum(const BatchDesc& P, int rank, unsigned seq, const double* x6, double* out6, bool fence,
@@ -375,7 +398,7 @@ DEV bool team_sum(const BatchDesc& P, int rank, unsigned seq, const double* x6, 
     } else {
         if (fence) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (tid == 0) {
+        if (tid < 64) {
             unsigned v[REC_WORDS];
             for (int k = 0; k < 6; ++k) pack_d(v, 2 * k, x6[k]);
             v[12] = v[13] = v[14] = 0;
@@ -691,7 +714,7 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
     auto merge = [&](double cbu, int ciu, double cbl, int cil, long long cnt, int ju, double aju, int jl,
                      double ajl) {
         double cau = 0.0, cal = 0.0;
-        if (tid == 0) {
+        if (tid < 64) {
             if (ciu != IDX_NONE) cau = ciu == ju ? aju : ciu == jl ? ajl : ld_agent(P.alpha + ciu);
             if (cil != IDX_NONE) cal = cil == ju ? aju : cil == jl ? ajl : ld_agent(P.alpha + cil);
         }
@@ -1006,7 +1029,7 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
             sh.red[wid][3] = v3; sh.red[wid][4] = v4; sh.red[wid][5] = v5;
         }
         __syncthreads();
-        if (tid == 0)
+        if (tid < 64)
             for (int w = 0; w < BNW; ++w)
                 for (int k = 0; k < 6; ++k) x6[k] += sh.red[w][k];
         __syncthreads();
@@ -1015,7 +1038,7 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
     // ---- completion: every member posts an acknowledgement and leaves; rank 0 waits for all of
     // them before it publishes the result (after which the host may reuse the team records)
     if (P.team > 1) {
-        if (tid == 0) {
+        if (tid < 64) {
             unsigned v[REC_WORDS];
             for (int k = 0; k < REC_WORDS; ++k) v[k] = 0;
             team_write(P.trec, P.team, rank, seq, v);

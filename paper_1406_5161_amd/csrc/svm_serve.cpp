@@ -122,8 +122,8 @@ struct Inspect {
 // Team size.  The requested one (params.grid_blocks) if set.  Otherwise the smallest team
 // whose members can each hold their segment (f, status, active list and rows) in LDS, so the
 // loop never reads rows from HBM, when a member then holds at least 512 rows and the team
-// needs at most TEAM_MAX workgroups; else about 3000 rows per workgroup (at most 16) streamed
-// from HBM.  Never more than the launch's workgroups.
+// needs at most TEAM_MAX workgroups; else about 1500 rows per workgroup (at most TEAM_MAX)
+// streamed from HBM.  Never more than the launch's workgroups.
 int team_size(const svm_problem_t* p, const Inspect& in, int workers, int requested) {
     const int cap = std::max(1, std::min(TEAM_MAX, workers));
     if (requested > 0) return std::min(requested, cap);
@@ -144,7 +144,7 @@ int team_size(const svm_problem_t* p, const Inspect& in, int workers, int reques
         const int b = (int)std::ceil((double)p->n / rows_cap);
         if (b <= cap) return std::max(1, b);
     }
-    return std::max(1, std::min(std::min(16, cap), (p->n + 2999) / 3000));
+    return std::max(1, std::min(cap, (p->n + 1499) / 1500));
 }
 
 int64_t shrink_h(const svm_params_t* q, int n) {

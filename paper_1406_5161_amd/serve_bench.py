@@ -29,7 +29,7 @@ def _pct(v, q):
 
 
 def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budget_gb: float = 64.0,
-        workers: int = 16, detail: list | None = None) -> dict:
+        workers: int = 16, detail: list | None = None, plain: bool = True) -> dict:
     """Runs both paths on the same trace; with `detail` (a list) appends one record per problem:
     shape, team size, iterations and device / host times of both paths."""
     import torch
@@ -47,7 +47,7 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
     ws = None
     lat_p, duals_p, its_p, ms_p = [], [], 0, []
     t0 = time.perf_counter()
-    for j, c in enumerate(cfgs):
+    for j, c in enumerate(cfgs if plain else []):
         now = time.perf_counter() - t0
         if now < arrivals[j]:
             time.sleep(arrivals[j] - now)
@@ -61,6 +61,9 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
             log("serving: plain loop %d/%d done at %.1f s" % (j + 1, num, time.perf_counter() - t0))
     span_p = time.perf_counter() - t0
     torch.cuda.synchronize()
+    if not plain:   # batched path only: no reference solves
+        lat_p, duals_p, ms_p = [0.0] * num, [1.0] * num, [(0.0, 0, 0)] * num
+        span_p = float("nan")
 
     # ---- server: submit at arrival, poll for completions
     alphas_s = [torch.zeros(c.data.n, dtype=torch.float64, device="cuda") for c in cfgs]
