@@ -1,0 +1,75 @@
+"""The shrinking-heuristic grid of the paper's evaluation (Table 3 and its figures): single and
+multi reconstruction, each with the fixed-count schedules random:2 / 500 / 1000 and the
+fraction schedules numsamples:5% / 10% / 50%, next to plain SMO without shrinking, on one
+workload.  For every run: seconds to KKT, time in the SMO loop and in reconstruction,
+iterations, reconstructions, shrink passes, samples shrunk, and the dual objective relative
+to the unshrunk run (every run stops at the same 2 eps gap, so the duals agree to within the
+eps band, not exactly).
+
+    python -m paper_1406_5161_amd.heuristics --config 2
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+from . import datagen as g
+
+GRID = [("none", g.SHRINK_NONE, g.KIND_FIXED, 0.0)]
+for mode_name, mode in (("single", g.SHRINK_SINGLE), ("multi", g.SHRINK_MULTI)):
+    for k in (2, 500, 1000):
+        GRID.append(("%s random:%d" % (mode_name, k), mode, g.KIND_FIXED, float(k)))
+    for frac in (0.05, 0.10, 0.50):
+        GRID.append(("%s numsamples:%d%%" % (mode_name, round(frac * 100)), mode, g.KIND_FRACTION, frac))
+
+
+def run(config: int, log=print, repeats: int = 1) -> list:
+    import torch
+    from . import svmhip as S
+    cfg = g.CONFIGS[config]()
+    data = cfg.data
+    dp = S.to_device(data)
+    alpha = torch.zeros(data.n, dtype=torch.float64, device="cuda")
+    f = torch.zeros(data.n, dtype=torch.float64, device="cuda")
+    base = S.make_params(cfg.C, cfg.gamma, cfg.eps)
+    ws = torch.empty(S.svm_train_workspace_size(dp, base), dtype=torch.uint8, device="cuda")
+    rc, _ = S.svm_train(dp, base, alpha, f, workspace=ws)   # warm-up
+    rows, ref = [], None
+    for name, mode, kind, param in GRID:
+        p = S.make_params(cfg.C, cfg.gamma, cfg.eps, mode, kind, param)
+        best = None
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, r = S.svm_train(dp, p, alpha, f, workspace=ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, r)
+        dt, r = best
+        if ref is None:
+            ref = r.dual_obj
+        row = {"heuristic": name, "rc": rc, "train_s": dt, "loop_s": r.ms_step * 1e-3, "recon_s": r.ms_recon * 1e-3,
+               "iterations": r.iterations, "n_recon": r.n_recon, "shrink_passes": r.shrink_passes,
+               "shrunk_total": r.shrunk_total, "n_sv": r.n_sv, "dual_obj": r.dual_obj,
+               "dual_rel_vs_none": (r.dual_obj - ref) / abs(ref)}
+        rows.append(row)
+        log("%-24s rc %d  %.3f s (loop %.3f, recon %.3f)  iters %d  recon %d  passes %d  shrunk %d  dual %+.2e"
+            % (name, rc, dt, row["loop_s"], row["recon_s"], r.iterations, r.n_recon, r.shrink_passes,
+               r.shrunk_total, row["dual_rel_vs_none"]))
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--repeats", type=int, default=1)
+    a = ap.parse_args()
+    rows = run(a.config, log=lambda *x: print(*x, file=sys.stderr, flush=True), repeats=a.repeats)
+    print(json.dumps({"workload": g.CONFIGS[a.config]().name, "grid": rows}))
+
+
+if __name__ == "__main__":
+    main()
