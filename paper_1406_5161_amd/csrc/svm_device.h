@@ -153,6 +153,29 @@ DEV void block_reduce_sel_all(double& bu, int& iu, double& bl, int& il, double* 
     }
 }
 
+// Block-wide reduction whose result only wave 0 needs: each wave reduces to its lane 63, one
+// barrier, then wave 0 alone reduces the NW wave results with DPP; the other waves return at
+// once.  Every lane of wave 0 holds the result; other lanes keep their wave's partial value.
+// The caller must not overwrite s_v / s_i before the next barrier.
+template <int BLOCK>
+DEV void block_reduce_sel_wave0(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i) {
+    constexpr int NW = BLOCK / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    wave_reduce_sel_to63(bu, iu, bl, il);
+    if (lane == 63) {
+        s_v[wid] = bu; s_i[wid] = iu;
+        s_v[NW + wid] = bl; s_i[NW + wid] = il;
+    }
+    __syncthreads();
+    if (wid == 0) {
+        bu = lane < NW ? s_v[lane] : INFINITY;
+        iu = lane < NW ? s_i[lane] : IDX_NONE;
+        bl = lane < NW ? s_v[NW + lane] : -INFINITY;
+        il = lane < NW ? s_i[NW + lane] : IDX_NONE;
+        wave_reduce_sel(bu, iu, bl, il);
+    }
+}
+
 // ------------------------------------------------------------------ pair update (eq:alphaup, eq:rho)
 
 struct PairNew {

@@ -464,7 +464,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         if (do_shrink) nrows = newcount;
         lap(1);
 
-        block_reduce_sel_all<BLOCK>(cbu, ciu, cbl, cil, s_v, s_i);
+        block_reduce_sel_wave0<BLOCK>(cbu, ciu, cbl, cil, s_v, s_i);   // wave 0 publishes
         // alpha and CSR extent of this workgroup's candidates: its own rows, which no other
         // workgroup writes, so they travel in the records instead of being re-read later
         double cau = 0.0, cal = 0.0;
