@@ -391,20 +391,37 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     }
                     if (gl == 0) work_nnz += (unsigned long long)(p1 - p0);
                     KT nn = 0, su = 0, sl2 = 0;
-                    for (int p = p0 + gl; p < p1; p += LPR) {
-                        int c;
-                        KT v;
-                        if constexpr (MODE == STEP_LDS_ALL) {
-                            c = COLL[p];
-                            v = A.pattern_only ? (KT)1 : (KT)VALL[p];
-                        } else {
-                            c = A.col[gbase + p];
-                            v = A.pattern_only ? (KT)1 : (KT)A.val[gbase + p];
+                    if constexpr (MODE == STEP_LDS_ALL) {
+                        for (int p = p0 + gl; p < p1; p += LPR) {
+                            const int c = COLL[p];
+                            const KT v = A.pattern_only ? (KT)1 : (KT)VALL[p];
+                            const float2 ul = (LAY == LAY_CSR_TABLE) ? pairv[c] : pairv[slot[c]];
+                            nn += v * v;
+                            su += v * (KT)ul.x;
+                            sl2 += v * (KT)ul.y;
                         }
-                        const float2 ul = (LAY == LAY_CSR_TABLE) ? pairv[c] : pairv[slot[c]];
-                        nn += v * v;
-                        su += v * (KT)ul.x;
-                        sl2 += v * (KT)ul.y;
+                    } else {
+                        // columns and values from HBM: CB of them are loaded before any is used
+                        constexpr int CB = 8;
+                        for (int pb = p0 + gl; pb < p1; pb += LPR * CB) {
+                            int cc[CB];
+                            float vf[CB];
+#pragma unroll
+                            for (int u = 0; u < CB; ++u) {
+                                const int p = pb + u * LPR;
+                                cc[u] = p < p1 ? A.col[gbase + p] : -1;
+                                vf[u] = (p < p1 && !A.pattern_only) ? A.val[gbase + p] : 1.f;
+                            }
+#pragma unroll
+                            for (int u = 0; u < CB; ++u) {
+                                if (cc[u] < 0) break;
+                                const KT v = (KT)vf[u];
+                                const float2 ul = (LAY == LAY_CSR_TABLE) ? pairv[cc[u]] : pairv[slot[cc[u]]];
+                                nn += v * v;
+                                su += v * (KT)ul.x;
+                                sl2 += v * (KT)ul.y;
+                            }
+                        }
                     }
 #pragma unroll
                     for (int off = LPR / 2; off > 0; off >>= 1) {
