@@ -763,6 +763,8 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
         }
         from_global();
     }
+    // the first exchange gathered the whole team: its tickets are all taken
+    if (rank == 0 && tid == 0) __hip_atomic_store(&P.res->started, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     lap(6);
     bool shrinking = P.shrink_mode != SVM_SHRINK_NONE;
     double thr = shrinking ? 20.0 * P.eps : 2.0 * P.eps;

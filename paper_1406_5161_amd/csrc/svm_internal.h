@@ -202,7 +202,7 @@ struct BatchResult {
     long long shrink_passes, shrunk_total;
     unsigned long long t_start, t_end;   // device wall clock (100 MHz) around the solve
     int32_t done;                        // set last (release) when the fields above are final
-    int32_t pad;
+    int32_t started;                     // set once the whole team has taken its tickets
 };
 
 // Outcome of a preparation job (validation, counts, dense packing) run by the serving loop.

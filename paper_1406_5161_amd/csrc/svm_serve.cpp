@@ -324,6 +324,8 @@ struct Pending {
 // A problem between admission and completion.
 struct Job {
     Pending w;
+    double ready_ms = 0.0;            // when it became ready to solve
+    double cost = 0.0;                // estimated work: n^2 x bytes per row
     int32_t slot = -1;                // descriptor slot of its current job (preparation, then solve)
     size_t base_off = 0, base_bytes = 0, team_off = 0, team_bytes = 0;
     Inspect in;
@@ -354,7 +356,7 @@ struct Server {
     std::mutex mu;
     std::deque<Pending> waiting;      // not admitted yet (slots or memory)
     std::map<int64_t, Job> prepping;  // preparation job published
-    std::deque<Job> ready;            // prepared, waiting for the team part's memory
+    std::vector<Job> ready;           // prepared, waiting for the loop to need work and for memory
     std::map<int64_t, Job> live;      // solve published, not yet observed done
     std::map<int64_t, svm_result_t> done;
     std::map<int64_t, int> failed;    // ticket -> error code
@@ -471,14 +473,41 @@ struct Server {
             j.team = team_size(&j.w.prob, j.in, workgroups, j.w.params.grid_blocks);
             while (j.team > 1 && j.base_bytes + prob_bytes(&j.w.prob, true, j.team, TEAM_MAX).team > budget) j.team /= 2;
             j.team_bytes = prob_bytes(&j.w.prob, true, j.team, TEAM_MAX).team;
+            const double row = j.w.prob.layout == SVM_CSR ? (bits_capable(&j.w.prob) && j.in.pattern
+                                                                 ? 4.0 * bits_wpr(j.w.prob.d)
+                                                                 : 6.0 * (double)j.in.nnz / j.w.prob.n)
+                                                          : 4.0 * dpad4(j.w.prob.d);
+            j.cost = (double)j.w.prob.n * (double)j.w.prob.n * row;
+            j.ready_ms = now_ms();
             ready.push_back(j);
         }
     }
 
-    // ready -> live: needs the team part of the solver state
+    // tickets published for solves whose team has not gathered yet
+    int64_t unstarted_tickets() const {
+        int64_t t = 0;
+        for (const auto& kv : live)
+            if (!__atomic_load_n(&results[kv.second.slot].started, __ATOMIC_ACQUIRE) &&
+                !__atomic_load_n(&results[kv.second.slot].done, __ATOMIC_ACQUIRE))
+                t += kv.second.team;
+        return t;
+    }
+
+    // ready -> live.  Solves are published only while the loop has fewer untaken tickets than
+    // workgroups, largest estimated work first (problems ready for more than 3 s first, in
+    // order), so a burst runs longest-first and the loop is never short of work.  Needs the
+    // team part of the solver state.
     void start_solves() {
-        while (!ready.empty()) {
-            Job& j = ready.front();
+        int64_t pending = unstarted_tickets();
+        while (!ready.empty() && pending < workgroups) {
+            const double now = now_ms();
+            size_t pick = 0;
+            for (size_t k = 1; k < ready.size(); ++k) {
+                const bool ak = now - ready[k].ready_ms > 3000.0, ap = now - ready[pick].ready_ms > 3000.0;
+                if (ak != ap ? ak : (ak ? ready[k].ready_ms < ready[pick].ready_ms : ready[k].cost > ready[pick].cost))
+                    pick = k;
+            }
+            Job& j = ready[pick];
             if (!arena.alloc(j.team_bytes, &j.team_off)) {
                 if (!j.counted_deferred) {
                     j.counted_deferred = true;
@@ -493,8 +522,9 @@ struct Server {
                       arena_mem + j.team_off, &results[slot], &D);
             j.slot = publish(D, j.team, false);
             ++n_admitted;
+            pending += j.team;
             live.emplace(j.w.ticket, j);
-            ready.pop_front();
+            ready.erase(ready.begin() + (long)pick);
         }
     }
 
