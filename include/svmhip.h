@@ -172,9 +172,12 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
  * each admitted problem, then solve it (a team per problem, as in
  * svm_train_batch) as slots and memory free up; a host thread admits waiting
  * problems as running ones complete and stops the loop after 2 s without
- * work (the next submit starts it again).  While the loop runs it holds all
- * but 8 compute units, so other device work of the process (copies,
- * kernels) runs on those 8.  FP32 kernel values only. */
+ * work (the next submit starts it again).  Prepared problems are handed to
+ * the loop largest estimated work (n^2 x bytes per row) first, and only while
+ * the loop is short of work, so a burst finishes longest-first; a problem
+ * prepared more than 3 s ago goes ahead of newer ones, oldest first.  While
+ * the loop runs it holds all but 8 compute units, so other device work of the
+ * process (copies, kernels) runs on those 8.  FP32 kernel values only. */
 int svm_server_create(size_t hbm_budget, int32_t max_slots, void** server);
 /* Queue a problem (its arrays must stay valid until the ticket completes).
  * alpha: n doubles (device) that receive the solution.  Returns a ticket; a

@@ -11,8 +11,10 @@
 // host memory as problems are admitted.  Admission needs a free slot (at most
 // max_slots problems in flight) and room for the problem's solver state in the
 // server's device-memory arena; otherwise the problem waits in a FIFO and is
-// admitted when a running one completes.  A monitor thread admits waiting
-// problems as others complete and parks the kernel after 2 s without work.
+// admitted when a running one completes.  Prepared problems are published
+// largest estimated work first while the kernel has fewer untaken tickets than
+// workgroups (see start_solves).  A monitor thread admits waiting problems as
+// others complete and parks the kernel after 2 s without work.
 //
 // Progress of teams: tickets are taken in order and a problem's tickets are
 // consecutive, so the oldest partly taken problem always has its missing
