@@ -27,8 +27,8 @@ constexpr size_t BATCH_LDS = BATCH_LDS_BYTES;
 
 struct BatchShared {
     BatchDesc P;
-    double v[2 * BNW];
-    int i[2 * BNW];
+    double v[SEL_LDS(BB)];
+    int i[SEL_LDS(BB)];
     int wc[BNW];
     double pair[4];
     double red[BNW][SUMR];

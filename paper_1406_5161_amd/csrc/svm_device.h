@@ -44,8 +44,7 @@ DEV bool better_up(double v, int i, double bv, int bi) { return v < bv || (v == 
 DEV bool better_low(double v, int i, double bv, int bi) { return v > bv || (v == bv && i < bi); }
 
 // DPP lane moves (gfx9 encodings): xor 1 and 2 inside a quad, rotate by 4 and 8 inside a
-// 16-lane row, then lane 15 -> next row and lane 31 -> rows 2-3.  Lanes a move does not
-// write keep `old`, which is always the reduction's identity here.
+// 16-lane row, then lane 15 -> next row and lane 31 -> rows 2-3.
 constexpr int DPP_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
 constexpr int DPP_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
 constexpr int DPP_ROR4 = 0x124;     // row_ror:4
@@ -53,37 +52,38 @@ constexpr int DPP_ROR8 = 0x128;     // row_ror:8
 constexpr int DPP_BCAST15 = 0x142;  // row_bcast:15
 constexpr int DPP_BCAST31 = 0x143;  // row_bcast:31
 
+// Exact two-threshold reductions (eq:bminmax): the up side keeps the least f, the low side the
+// largest, ties to the lowest sample id.  Values are only compared, never combined, so any
+// order of reduction picks the same winner.  Each runs in two passes over the lanes: first
+// the extreme value, then the lowest id among the lanes holding it; the winner keeps its own
+// value (an f equal to the extreme can differ from it only in the sign of a zero).  Lanes
+// without a candidate hold (+inf, IDX_NONE) on the up side and (-inf, IDX_NONE) on the low side.
+//
+// Lane moves: quad swaps and row rotations by 4 and 8 leave every lane of a 16-lane row with
+// the row's result; the two row broadcasts then carry it to lane 63 only (the other lanes of
+// rows the broadcast does not write end with unspecified values, which nothing reads).
 template <int CTRL, int ROWS>
-DEV int dpp_i(int old, int v) {
-    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+DEV int mov_dpp(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, ROWS, 0xF, false);
 }
 template <int CTRL, int ROWS>
-DEV double dpp_d(double old, double v) {
-    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
-    const int lo = dpp_i<CTRL, ROWS>((int)(unsigned)(o & 0xffffffffll), (int)(unsigned)(x & 0xffffffffll));
-    const int hi = dpp_i<CTRL, ROWS>((int)(o >> 32), (int)(x >> 32));
+DEV double mov_dpp_d(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = mov_dpp<CTRL, ROWS>((int)(unsigned)(x & 0xffffffffll));
+    const int hi = mov_dpp<CTRL, ROWS>((int)(x >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-
 template <int CTRL, int ROWS>
-DEV void sel_step(double& bu, int& iu, double& bl, int& il) {
-    const double ou = dpp_d<CTRL, ROWS>(INFINITY, bu);
-    const int oiu = dpp_i<CTRL, ROWS>(IDX_NONE, iu);
-    const double ol = dpp_d<CTRL, ROWS>(-INFINITY, bl);
-    const int oil = dpp_i<CTRL, ROWS>(IDX_NONE, il);
-    if (better_up(ou, oiu, bu, iu)) { bu = ou; iu = oiu; }
-    if (better_low(ol, oil, bl, il)) { bl = ol; il = oil; }
+DEV void ext_step(double& mu, double& ml) {
+    const double ou = mov_dpp_d<CTRL, ROWS>(mu), ol = mov_dpp_d<CTRL, ROWS>(ml);
+    mu = ou < mu ? ou : mu;
+    ml = ol > ml ? ol : ml;
 }
-
-// Wave-wide two-threshold reduction; the result is valid in lane 63 (and returned in every lane
-// by wave_reduce_sel).  Only DPP moves: no LDS traffic.
-DEV void wave_reduce_sel_to63(double& bu, int& iu, double& bl, int& il) {
-    sel_step<DPP_XOR1, 0xF>(bu, iu, bl, il);
-    sel_step<DPP_XOR2, 0xF>(bu, iu, bl, il);
-    sel_step<DPP_ROR4, 0xF>(bu, iu, bl, il);
-    sel_step<DPP_ROR8, 0xF>(bu, iu, bl, il);
-    sel_step<DPP_BCAST15, 0xA>(bu, iu, bl, il);
-    sel_step<DPP_BCAST31, 0xC>(bu, iu, bl, il);
+// (ids: the move's unwritten lanes hold IDX_NONE, so the min folds into one DPP instruction)
+template <int CTRL, int ROWS>
+DEV void idx_step(int& ju, int& jl) {
+    ju = min(ju, __builtin_amdgcn_update_dpp(IDX_NONE, ju, CTRL, ROWS, 0xF, false));
+    jl = min(jl, __builtin_amdgcn_update_dpp(IDX_NONE, jl, CTRL, ROWS, 0xF, false));
 }
 
 DEV double readlane_d(double v, int lane) {
@@ -93,12 +93,34 @@ DEV double readlane_d(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Wave-wide two-threshold reduction; every lane returns the winners.  DPP moves and lane
+// reads only: no LDS traffic.  Needs the whole wave active.
 DEV void wave_reduce_sel(double& bu, int& iu, double& bl, int& il) {
-    wave_reduce_sel_to63(bu, iu, bl, il);
-    bu = readlane_d(bu, 63);
-    iu = __builtin_amdgcn_readlane(iu, 63);
-    bl = readlane_d(bl, 63);
-    il = __builtin_amdgcn_readlane(il, 63);
+    double mu = bu, ml = bl;
+    ext_step<DPP_XOR1, 0xF>(mu, ml);
+    ext_step<DPP_XOR2, 0xF>(mu, ml);
+    ext_step<DPP_ROR4, 0xF>(mu, ml);
+    ext_step<DPP_ROR8, 0xF>(mu, ml);
+    ext_step<DPP_BCAST15, 0xA>(mu, ml);
+    ext_step<DPP_BCAST31, 0xC>(mu, ml);
+    mu = readlane_d(mu, 63);
+    ml = readlane_d(ml, 63);
+    int ju = bu == mu ? iu : IDX_NONE, jl = bl == ml ? il : IDX_NONE;
+    idx_step<DPP_XOR1, 0xF>(ju, jl);
+    idx_step<DPP_XOR2, 0xF>(ju, jl);
+    idx_step<DPP_ROR4, 0xF>(ju, jl);
+    idx_step<DPP_ROR8, 0xF>(ju, jl);
+    idx_step<DPP_BCAST15, 0xA>(ju, jl);
+    idx_step<DPP_BCAST31, 0xC>(ju, jl);
+    ju = __builtin_amdgcn_readlane(ju, 63);
+    jl = __builtin_amdgcn_readlane(jl, 63);
+    // the lanes holding the winners (in an empty side every lane holds the same empty entry)
+    const int wu = __builtin_ctzll(__ballot(iu == ju && bu == mu));
+    const int wl = __builtin_ctzll(__ballot(il == jl && bl == ml));
+    bu = readlane_d(bu, wu);
+    bl = readlane_d(bl, wl);
+    iu = ju;
+    il = jl;
 }
 
 template <typename T>
@@ -120,60 +142,59 @@ DEV void st_agent(unsigned long long* p, unsigned long long v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int BLOCK>
-DEV void block_reduce_sel_all(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i);
+// LDS the block reductions below need: SEL_LDS(BLOCK) doubles and as many ints.
+constexpr int SEL_LDS(int block) { return block / 32; }
 
-// Block-wide reduction of the selection candidates; result valid in every thread.
+// Each wave's winners into LDS: s_v / s_i [wave] up side, [BLOCK/64 + wave] low side.
 template <int BLOCK>
-DEV void block_reduce_sel(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i) {
+DEV void waves_to_lds(double bu, int iu, double bl, int il, double* s_v, int* s_i) {
     constexpr int NW = BLOCK / 64;
-    block_reduce_sel_all<BLOCK>(bu, iu, bl, il, s_v, s_i);
-    __syncthreads();
+    const int wid = threadIdx.x >> 6;
+    wave_reduce_sel(bu, iu, bl, il);
+    if ((threadIdx.x & 63) == 0) {
+        s_v[wid] = bu; s_i[wid] = iu;
+        s_v[NW + wid] = bl; s_i[NW + wid] = il;
+    }
+}
+
+// The wave results of waves_to_lds reduced by one wave (every lane of it gets the winners).
+template <int BLOCK>
+DEV void wave_reduce_waves(double& bu, int& iu, double& bl, int& il, const double* s_v, const int* s_i) {
+    constexpr int NW = BLOCK / 64;
+    const int lane = threadIdx.x & 63;
+    bu = lane < NW ? s_v[lane] : INFINITY;
+    iu = lane < NW ? s_i[lane] : IDX_NONE;
+    bl = lane < NW ? s_v[NW + lane] : -INFINITY;
+    il = lane < NW ? s_i[NW + lane] : IDX_NONE;
+    wave_reduce_sel(bu, iu, bl, il);
 }
 
 // Block-wide reduction whose result every thread holds on return; one barrier.  The
 // caller must not overwrite s_v / s_i before the next barrier.
 template <int BLOCK>
 DEV void block_reduce_sel_all(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i) {
-    constexpr int NW = BLOCK / 64;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    wave_reduce_sel_to63(bu, iu, bl, il);
-    if (lane == 63) {
-        s_v[wid] = bu; s_i[wid] = iu;
-        s_v[NW + wid] = bl; s_i[NW + wid] = il;
-    }
+    waves_to_lds<BLOCK>(bu, iu, bl, il, s_v, s_i);
     __syncthreads();
-    bu = s_v[0]; iu = s_i[0]; bl = s_v[NW]; il = s_i[NW];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) {
-        const double vu = s_v[w], vl = s_v[NW + w];
-        const int ju = s_i[w], jl = s_i[NW + w];
-        if (better_up(vu, ju, bu, iu)) { bu = vu; iu = ju; }
-        if (better_low(vl, jl, bl, il)) { bl = vl; il = jl; }
-    }
+    wave_reduce_waves<BLOCK>(bu, iu, bl, il, s_v, s_i);
 }
 
-// Block-wide reduction whose result only wave 0 needs: each wave reduces to its lane 63, one
-// barrier, then wave 0 alone reduces the NW wave results with DPP; the other waves return at
-// once.  Every lane of wave 0 holds the result; other lanes keep their wave's partial value.
-// The caller must not overwrite s_v / s_i before the next barrier.
+// Block-wide reduction of the selection candidates; result valid in every thread, and s_v /
+// s_i free again on return.
+template <int BLOCK>
+DEV void block_reduce_sel(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i) {
+    block_reduce_sel_all<BLOCK>(bu, iu, bl, il, s_v, s_i);
+    __syncthreads();
+}
+
+// Block-wide reduction whose result only wave 0 needs: the wave results go to LDS, one
+// barrier, then wave 0 alone reduces them; the other waves return at once.  Every lane of
+// wave 0 holds the result; other lanes keep their own candidates.  The caller must not
+// overwrite s_v / s_i before the next barrier.
 template <int BLOCK>
 DEV void block_reduce_sel_wave0(double& bu, int& iu, double& bl, int& il, double* s_v, int* s_i) {
-    constexpr int NW = BLOCK / 64;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    wave_reduce_sel_to63(bu, iu, bl, il);
-    if (lane == 63) {
-        s_v[wid] = bu; s_i[wid] = iu;
-        s_v[NW + wid] = bl; s_i[NW + wid] = il;
-    }
+    waves_to_lds<BLOCK>(bu, iu, bl, il, s_v, s_i);
     __syncthreads();
-    if (wid == 0) {
-        bu = lane < NW ? s_v[lane] : INFINITY;
-        iu = lane < NW ? s_i[lane] : IDX_NONE;
-        bl = lane < NW ? s_v[NW + lane] : -INFINITY;
-        il = lane < NW ? s_i[NW + lane] : IDX_NONE;
-        wave_reduce_sel(bu, iu, bl, il);
-    }
+    if ((threadIdx.x >> 6) == 0) wave_reduce_waves<BLOCK>(bu, iu, bl, il, s_v, s_i);
 }
 
 // ------------------------------------------------------------------ pair update (eq:alphaup, eq:rho)

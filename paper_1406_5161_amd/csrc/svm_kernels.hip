@@ -156,8 +156,8 @@ __global__ __launch_bounds__(256) void select_partial_kernel(const int32_t* seg_
                                                              const int32_t* act, const double* __restrict__ f,
                                                              const double* __restrict__ alpha,
                                                              const int8_t* __restrict__ y, double C, Rec* rec) {
-    __shared__ double s_v[8];
-    __shared__ int s_i[8];
+    __shared__ double s_v[SEL_LDS(256)];
+    __shared__ int s_i[SEL_LDS(256)];
     const int b = blockIdx.x;
     const int s0 = seg_start[b], c = cnt[b];
     double bu = INFINITY, bl = -INFINITY;
@@ -179,8 +179,8 @@ __global__ __launch_bounds__(256) void select_partial_kernel(const int32_t* seg_
 }
 
 __global__ __launch_bounds__(1024) void select_merge_kernel(int G, const Rec* rec, const double* alpha, Ctl* ctl) {
-    __shared__ double s_v[32];
-    __shared__ int s_i[32];
+    __shared__ double s_v[SEL_LDS(1024)];
+    __shared__ int s_i[SEL_LDS(1024)];
     __shared__ long long s_c[16];
     double bu = INFINITY, bl = -INFINITY;
     int iu = IDX_NONE, il = IDX_NONE;

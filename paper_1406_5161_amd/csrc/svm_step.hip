@@ -86,8 +86,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     constexpr bool BITS = LAY == LAY_BITS;
     constexpr bool CSR = LAY == LAY_CSR_TABLE || LAY == LAY_CSR_SLOT;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double s_v[4 * NW];
-    __shared__ int s_i[2 * NW];
+    __shared__ double s_v[SEL_LDS(BLOCK)];
+    __shared__ int s_i[SEL_LDS(BLOCK)];
     __shared__ int s_wc[NW];
     __shared__ double s_pair[4];     // K_ul, |u|^2, |l|^2
     __shared__ double s_sel[4];
