@@ -94,26 +94,35 @@ DEV double readlane_d(double v, int lane) {
 }
 
 // Wave-wide two-threshold reduction; every lane returns the winners.  DPP moves and lane
-// reads only: no LDS traffic.  Needs the whole wave active.
+// reads only: no LDS traffic.  Needs the whole wave active.  With LANES = 16 only lanes 0-15
+// may hold candidates (the others must hold the empty entries), and the broadcasts between
+// rows are skipped.
+template <int LANES = 64>
 DEV void wave_reduce_sel(double& bu, int& iu, double& bl, int& il) {
+    static_assert(LANES == 16 || LANES == 64, "a row or the whole wave");
+    constexpr int LAST = LANES - 1;   // a lane that ends with the result
     double mu = bu, ml = bl;
     ext_step<DPP_XOR1, 0xF>(mu, ml);
     ext_step<DPP_XOR2, 0xF>(mu, ml);
     ext_step<DPP_ROR4, 0xF>(mu, ml);
     ext_step<DPP_ROR8, 0xF>(mu, ml);
-    ext_step<DPP_BCAST15, 0xA>(mu, ml);
-    ext_step<DPP_BCAST31, 0xC>(mu, ml);
-    mu = readlane_d(mu, 63);
-    ml = readlane_d(ml, 63);
+    if constexpr (LANES == 64) {
+        ext_step<DPP_BCAST15, 0xA>(mu, ml);
+        ext_step<DPP_BCAST31, 0xC>(mu, ml);
+    }
+    mu = readlane_d(mu, LAST);
+    ml = readlane_d(ml, LAST);
     int ju = bu == mu ? iu : IDX_NONE, jl = bl == ml ? il : IDX_NONE;
     idx_step<DPP_XOR1, 0xF>(ju, jl);
     idx_step<DPP_XOR2, 0xF>(ju, jl);
     idx_step<DPP_ROR4, 0xF>(ju, jl);
     idx_step<DPP_ROR8, 0xF>(ju, jl);
-    idx_step<DPP_BCAST15, 0xA>(ju, jl);
-    idx_step<DPP_BCAST31, 0xC>(ju, jl);
-    ju = __builtin_amdgcn_readlane(ju, 63);
-    jl = __builtin_amdgcn_readlane(jl, 63);
+    if constexpr (LANES == 64) {
+        idx_step<DPP_BCAST15, 0xA>(ju, jl);
+        idx_step<DPP_BCAST31, 0xC>(ju, jl);
+    }
+    ju = __builtin_amdgcn_readlane(ju, LAST);
+    jl = __builtin_amdgcn_readlane(jl, LAST);
     // the lanes holding the winners (in an empty side every lane holds the same empty entry)
     const int wu = __builtin_ctzll(__ballot(iu == ju && bu == mu));
     const int wl = __builtin_ctzll(__ballot(il == jl && bl == ml));
@@ -150,7 +159,8 @@ template <int BLOCK>
 DEV void waves_to_lds(double bu, int iu, double bl, int il, double* s_v, int* s_i) {
     constexpr int NW = BLOCK / 64;
     const int wid = threadIdx.x >> 6;
-    wave_reduce_sel(bu, iu, bl, il);
+    // a wave without candidates holds the empty entries in every lane already
+    if (__ballot(iu != IDX_NONE || il != IDX_NONE)) wave_reduce_sel(bu, iu, bl, il);
     if ((threadIdx.x & 63) == 0) {
         s_v[wid] = bu; s_i[wid] = iu;
         s_v[NW + wid] = bl; s_i[NW + wid] = il;
@@ -166,7 +176,7 @@ DEV void wave_reduce_waves(double& bu, int& iu, double& bl, int& il, const doubl
     iu = lane < NW ? s_i[lane] : IDX_NONE;
     bl = lane < NW ? s_v[NW + lane] : -INFINITY;
     il = lane < NW ? s_i[NW + lane] : IDX_NONE;
-    wave_reduce_sel(bu, iu, bl, il);
+    wave_reduce_sel<(NW <= 16 ? 16 : 64)>(bu, iu, bl, il);
 }
 
 // Block-wide reduction whose result every thread holds on return; one barrier.  The
