@@ -132,6 +132,34 @@ DEV void wave_reduce_sel(double& bu, int& iu, double& bl, int& il) {
     il = jl;
 }
 
+// Sums of two ints over lanes 0-31 (lanes 32-63 ignored), returned in every lane: row sums by
+// DPP (quad swaps, rotations by 4 and 8), then row 0 added into row 1 and read from lane 31.
+DEV void sum2_lanes32(int& a, int& b) {
+    a += __builtin_amdgcn_update_dpp(0, a, DPP_XOR1, 0xF, 0xF, false);
+    b += __builtin_amdgcn_update_dpp(0, b, DPP_XOR1, 0xF, 0xF, false);
+    a += __builtin_amdgcn_update_dpp(0, a, DPP_XOR2, 0xF, 0xF, false);
+    b += __builtin_amdgcn_update_dpp(0, b, DPP_XOR2, 0xF, 0xF, false);
+    a += __builtin_amdgcn_update_dpp(0, a, DPP_ROR4, 0xF, 0xF, false);
+    b += __builtin_amdgcn_update_dpp(0, b, DPP_ROR4, 0xF, 0xF, false);
+    a += __builtin_amdgcn_update_dpp(0, a, DPP_ROR8, 0xF, 0xF, false);
+    b += __builtin_amdgcn_update_dpp(0, b, DPP_ROR8, 0xF, 0xF, false);
+    a += __builtin_amdgcn_update_dpp(0, a, DPP_BCAST15, 0xA, 0xF, false);
+    b += __builtin_amdgcn_update_dpp(0, b, DPP_BCAST15, 0xA, 0xF, false);
+    a = __builtin_amdgcn_readlane(a, 31);
+    b = __builtin_amdgcn_readlane(b, 31);
+}
+
+// Float sum over the wave by DPP (row sums, then rows 0-3 into lane 63), returned in every lane.
+DEV float wave_sum_dpp(float v) {
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_XOR1, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_XOR2, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_ROR4, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_ROR8, 0xF, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_BCAST15, 0xA, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_BCAST31, 0xC, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
 template <typename T>
 DEV T wave_sum(T v) {
 #pragma unroll

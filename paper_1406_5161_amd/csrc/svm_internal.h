@@ -11,7 +11,7 @@
 namespace svm {
 
 // sample layouts inside the library
-// LAY_BITS (batched solver only): CSR rows whose values are all 1.0 with d <= BITS_MAX_D, kept
+// LAY_BITS: CSR rows whose values are all 1.0 with d <= BITS_MAX_D (at most 32 words), kept
 // as bitsets of wpr 32-bit words per row; a dot product is a popcount of an AND.
 enum : int { LAY_DENSE = 0, LAY_CSR_TABLE = 1, LAY_CSR_SLOT = 2, LAY_BITS = 3 };
 constexpr int BITS_MAX_D = 1024;

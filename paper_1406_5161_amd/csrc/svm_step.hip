@@ -213,9 +213,22 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         if (LAY == LAY_DENSE) {
             const float* xu = A.x + (size_t)iu * A.dpad;
             const float* xl = A.x + (size_t)il * A.dpad;
-            for (int k = tid; k < A.dpad; k += BLOCK) pairv[k] = make_float2(xu[k], xl[k]);
-            __syncthreads();
-            if constexpr (std::is_same<KT, double>::value) {
+            if constexpr (std::is_same<KT, float>::value) {
+                // wave 0 alone stages the rows and sums the squared differences
+                if (wid == 0) {
+                    float a = 0.f;
+                    for (int k = lane; k < A.dpad; k += 64) {
+                        const float u = xu[k], l = xl[k];
+                        pairv[k] = make_float2(u, l);
+                        const float t = u - l;
+                        a = fmaf(t, t, a);
+                    }
+                    a = wave_sum_dpp(a);
+                    if (lane == 0) s_pair[0] = (double)expf(-(float)A.gamma * a);
+                }
+            } else {
+                for (int k = tid; k < A.dpad; k += BLOCK) pairv[k] = make_float2(xu[k], xl[k]);
+                __syncthreads();
                 // sequential in k: the same rounding as the FP64 reference
                 if (tid == 0) {
 #pragma clang fp contract(off)
@@ -226,32 +239,22 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     }
                     s_pair[0] = exp(-A.gamma * a);
                 }
-            } else {
-                if (wid == 0) {
-                    float a = 0.f;
-                    for (int k = lane; k < A.dpad; k += 64) {
-                        float t = pairv[k].x - pairv[k].y;
-                        a = fmaf(t, t, a);
-                    }
-                    a = wave_sum(a);
-                    if (lane == 0) s_pair[0] = (double)expf(-(float)A.gamma * a);
-                }
             }
         } else if constexpr (BITS) {
-            const int wpr = A.wpr;
-            for (int k = tid; k < 2 * wpr; k += BLOCK)
-                pairb[k] = k < wpr ? A.bits[(size_t)iu * wpr + k] : A.bits[(size_t)il * wpr + (k - wpr)];
-            __syncthreads();
+            // wave 0 alone: lane k < wpr (at most 32) stages word k of both rows and counts its
+            // bits; |u| and |l| travel packed 16 bits apart (each at most d <= 1024)
             if (wid == 0) {
-                int cu = 0, cl = 0, cd = 0;
-                for (int k = lane; k < wpr; k += 64) {
-                    cu += __popc(pairb[k]);
-                    cl += __popc(pairb[wpr + k]);
-                    cd += __popc(pairb[k] & pairb[wpr + k]);
+                const int wpr = A.wpr;
+                uint32_t wu = 0, wl = 0;
+                if (lane < wpr) {
+                    wu = A.bits[(size_t)iu * wpr + lane];
+                    wl = A.bits[(size_t)il * wpr + lane];
+                    pairb[lane] = wu;
+                    pairb[wpr + lane] = wl;
                 }
-                cu = wave_sum(cu);
-                cl = wave_sum(cl);
-                cd = wave_sum(cd);
+                int c2 = __popc(wu) | (__popc(wl) << 16), cd = __popc(wu & wl);
+                sum2_lanes32(c2, cd);
+                const int cu = c2 & 0xffff, cl = c2 >> 16;
                 if (lane == 0) {
                     KT d2 = (KT)cu + (KT)cl - (KT)2 * (KT)cd;
                     if (d2 < (KT)0) d2 = (KT)0;
