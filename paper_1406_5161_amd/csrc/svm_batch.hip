@@ -826,7 +826,7 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
                             const float t = pairv[k].x - pairv[k].y;
                             a = fmaf(t, t, a);
                         }
-                        sk = (double)expf(-(float)P.gamma * a);
+                        sk = (double)kexp(-(float)P.gamma * a);
                     }
                     sh.pair[0] = sk;
                 }

@@ -167,7 +167,10 @@ DEV T wave_sum(T v) {
     return v;
 }
 
-DEV float kexp(float v) { return expf(v); }
+// FP32 kernel values: e^v as 2^(v log2 e) on the hardware base-2 exponential (about 1 ulp; the
+// product adds one rounding, an error of the same order as forming v = -gamma d^2 in FP32).
+// Results below the smallest normal float may flush to 0.
+DEV float kexp(float v) { return __builtin_amdgcn_exp2f(v * 1.44269504088896341f); }
 DEV double kexp(double v) { return exp(v); }
 
 DEV double ld_agent(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }

@@ -611,7 +611,7 @@ __global__ __launch_bounds__(SUM_BLOCK) void kernel_sum_mfma_kernel(SumArgs A) {
                 const int row = 16 * wid + 4 * mk + i;
                 float d2 = s_na[row] + nbc - 2.f * dv[i];
                 d2 = d2 < 0.f ? 0.f : d2;
-                acc[i] += cbv * (double)expf(-gam * d2);
+                acc[i] += cbv * (double)kexp(-gam * d2);
             }
         }
     }

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                         a = fmaf(t, t, a);
                     }
                     a = wave_sum_dpp(a);
-                    if (lane == 0) s_pair[0] = (double)expf(-(float)A.gamma * a);
+                    if (lane == 0) s_pair[0] = (double)kexp(-(float)A.gamma * a);
                 }
             } else {
                 for (int k = tid; k < A.dpad; k += BLOCK) pairv[k] = make_float2(xu[k], xl[k]);
