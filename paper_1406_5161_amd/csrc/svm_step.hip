@@ -552,10 +552,14 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                 const unsigned long long* w = A.rec[par * G + tid].w;
                 unsigned v[REC_WORDS];
                 const unsigned long long t0 = wall_clock64();
-                // wait on the last word written first, then read the record
-                while ((unsigned)(ld_agent(w + REC_WORDS - 1) >> 32) != tg) {
-                    if (wall_clock64() - t0 > A.spin_limit) { ab = 1; break; }
-                    __builtin_amdgcn_s_sleep(1);
+                // with more than 64 records, poll the last word written before reading the
+                // record (whole-record polls by every lane of several waves contend); with at
+                // most 64, poll whole records (one memory round trip fewer)
+                if (G > 64) {
+                    while ((unsigned)(ld_agent(w + REC_WORDS - 1) >> 32) != tg) {
+                        if (wall_clock64() - t0 > A.spin_limit) { ab = 1; break; }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
                 }
                 for (; !ab;) {
                     bool ok = true;
