@@ -655,27 +655,34 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
     const int nnz0 = (dense || bits) ? 0 : P.row_ptr[seg0];
     const int nnz_seg = (dense || bits) ? 0 : P.row_ptr[seg1] - nnz0;
     const bool pat = P.pattern_only != 0;
+    // this member's state (f, status, active list) lives in LDS when it fits (`res`), and its
+    // rows too when they also fit (`rres`); otherwise the rows stream from HBM
+    const size_t state_bytes = al16(sizeof(double) * (size_t)m) + al16((size_t)m) + al16(sizeof(uint16_t) * (size_t)m);
+    size_t rows_bytes;
+    if (dense) {
+        rows_bytes = al16(sizeof(float) * (size_t)m * P.dpad);
+    } else if (bits) {
+        rows_bytes = al16(sizeof(uint32_t) * (size_t)m * P.wpr);
+    } else {
+        rows_bytes = al16(sizeof(uint32_t) * (size_t)(m + 1)) + al16(sizeof(uint16_t) * (size_t)nnz_seg) +
+                     (pat ? 0 : al16(sizeof(float) * (size_t)nnz_seg));
+    }
+    const size_t seg_room = BATCH_LDS - (size_t)(segmem - dyn);
+    const bool res = state_bytes <= seg_room && m <= 65535;
+    const bool rres = res && state_bytes + rows_bytes <= seg_room && (dense || P.d <= 65536);
     size_t so = al16(sizeof(double) * (size_t)m);
     double* f_l = reinterpret_cast<double*>(segmem);
-    float* x_l = reinterpret_cast<float*>(segmem + so);
-    uint32_t* bits_l = reinterpret_cast<uint32_t*>(segmem + so);
-    uint32_t* off_l = reinterpret_cast<uint32_t*>(segmem + so);
-    if (dense) {
-        so += al16(sizeof(float) * (size_t)m * P.dpad);
-    } else if (bits) {
-        so += al16(sizeof(uint32_t) * (size_t)m * P.wpr);
-    } else {
-        so += al16(sizeof(uint32_t) * (size_t)(m + 1));
-    }
-    uint16_t* cols_l = reinterpret_cast<uint16_t*>(segmem + so);
-    if (!dense && !bits) so += al16(sizeof(uint16_t) * (size_t)nnz_seg);
-    float* vals_l = reinterpret_cast<float*>(segmem + so);
-    if (!dense && !bits && !pat) so += al16(sizeof(float) * (size_t)nnz_seg);
     uint8_t* st_l = segmem + so;
     so += al16((size_t)m);
     uint16_t* act_l = reinterpret_cast<uint16_t*>(segmem + so);
     so += al16(sizeof(uint16_t) * (size_t)m);
-    const bool res = (size_t)(segmem - dyn) + so <= BATCH_LDS && m <= 65535 && (dense || P.d <= 65536);
+    float* x_l = reinterpret_cast<float*>(segmem + so);
+    uint32_t* bits_l = reinterpret_cast<uint32_t*>(segmem + so);
+    uint32_t* off_l = reinterpret_cast<uint32_t*>(segmem + so);
+    if (!dense && !bits) so += al16(sizeof(uint32_t) * (size_t)(m + 1));
+    uint16_t* cols_l = reinterpret_cast<uint16_t*>(segmem + so);
+    if (!dense && !bits) so += al16(sizeof(uint16_t) * (size_t)nnz_seg);
+    float* vals_l = reinterpret_cast<float*>(segmem + so);
     const unsigned long long t_start = wall_clock64();
     unsigned seq = 1;
     bool alive = true;
@@ -745,7 +752,7 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
         }
         __syncthreads();
     };
-    if (res) {
+    if (rres) {
         if (dense) {
             const float4* src = reinterpret_cast<const float4*>(P.x + (size_t)seg0 * P.dpad);
             float4* dst = reinterpret_cast<float4*>(x_l);
@@ -761,8 +768,8 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
                 if (!pat) vals_l[k] = P.val[nnz0 + k];
             }
         }
-        from_global();
     }
+    if (res) from_global();
     // the first exchange gathered the whole team: its tickets are all taken
     if (rank == 0 && tid == 0) __hip_atomic_store(&P.res->started, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     lap(6);
@@ -808,45 +815,53 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
             if (dense) {
                 const float* xu = P.x + (size_t)iu * P.dpad;
                 const float* xl = P.x + (size_t)il * P.dpad;
-                for (int k = tid; k < P.dpad; k += BB) pairv[k] = make_float2(xu[k], xl[k]);
-                __syncthreads();
-                if (tid == 0) {
-                    double sk;
-                    if constexpr (std::is_same<KT, double>::value) {
+                if constexpr (std::is_same<KT, double>::value) {
+                    for (int k = tid; k < P.dpad; k += BB) pairv[k] = make_float2(xu[k], xl[k]);
+                    __syncthreads();
+                    if (tid == 0) {
+                        // sequential in k: the same rounding as the FP64 reference
 #pragma clang fp contract(off)
                         double a = 0.0;
                         for (int k = 0; k < P.dpad; ++k) {
                             const double t = (double)pairv[k].x - (double)pairv[k].y;
                             a = a + t * t;
                         }
-                        sk = exp(-P.gamma * a);
-                    } else {
-                        float a = 0.f;
-                        for (int k = 0; k < P.dpad; ++k) {
-                            const float t = pairv[k].x - pairv[k].y;
-                            a = fmaf(t, t, a);
-                        }
-                        sk = (double)kexp(-(float)P.gamma * a);
+                        sh.pair[0] = exp(-P.gamma * a);
                     }
-                    sh.pair[0] = sk;
+                } else if (wid == 0) {
+                    // wave 0 alone stages the rows and sums the squared differences
+                    float a = 0.f;
+                    for (int k = lane; k < P.dpad; k += 64) {
+                        const float u = xu[k], l = xl[k];
+                        pairv[k] = make_float2(u, l);
+                        const float t = u - l;
+                        a = fmaf(t, t, a);
+                    }
+                    a = wave_sum_dpp(a);
+                    if (lane == 0) sh.pair[0] = (double)kexp(-(float)P.gamma * a);
                 }
             } else if (bits) {
-                const int wpr = P.wpr;
-                for (int k = tid; k < 2 * wpr; k += BB)
-                    pairb[k] = k < wpr ? P.bits[(size_t)iu * wpr + k] : P.bits[(size_t)il * wpr + (k - wpr)];
-                __syncthreads();
-                if (tid == 0) {
-                    int cu = 0, cl = 0, cd = 0;
-                    for (int k = 0; k < wpr; ++k) {
-                        cu += __popc(pairb[k]);
-                        cl += __popc(pairb[wpr + k]);
-                        cd += __popc(pairb[k] & pairb[wpr + k]);
+                // wave 0 alone: lane k < wpr (at most 32) stages word k of both rows and counts its
+                // bits; |u| and |l| travel packed 16 bits apart (each at most d <= 1024)
+                if (wid == 0) {
+                    const int wpr = P.wpr;
+                    uint32_t wu = 0, wl = 0;
+                    if (lane < wpr) {
+                        wu = P.bits[(size_t)iu * wpr + lane];
+                        wl = P.bits[(size_t)il * wpr + lane];
+                        pairb[lane] = wu;
+                        pairb[wpr + lane] = wl;
                     }
-                    KT d2 = (KT)cu + (KT)cl - (KT)2 * (KT)cd;
-                    if (d2 < (KT)0) d2 = (KT)0;
-                    sh.pair[0] = (double)kexp((KT)(-(KT)P.gamma * d2));
-                    sh.pair[1] = (double)cu;
-                    sh.pair[2] = (double)cl;
+                    int c2 = __popc(wu) | (__popc(wl) << 16), cd = __popc(wu & wl);
+                    sum2_lanes32(c2, cd);
+                    const int cu = c2 & 0xffff, cl = c2 >> 16;
+                    if (lane == 0) {
+                        KT d2 = (KT)cu + (KT)cl - (KT)2 * (KT)cd;
+                        if (d2 < (KT)0) d2 = (KT)0;
+                        sh.pair[0] = (double)kexp((KT)(-(KT)P.gamma * d2));
+                        sh.pair[1] = (double)cu;
+                        sh.pair[2] = (double)cl;
+                    }
                 }
             } else {
                 const int pu0 = P.row_ptr[iu], pu1 = P.row_ptr[iu + 1];
@@ -907,9 +922,9 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
                 }
                 KT du2[RPT], dl2[RPT];
                 if (bits)
-                    rows_dist_bits<KT, RPT>(P.wpr, res ? bits_l : P.bits, pairb, res ? rr : ii, vv, nuu, nll, du2,
+                    rows_dist_bits<KT, RPT>(P.wpr, rres ? bits_l : P.bits, pairb, rres ? rr : ii, vv, nuu, nll, du2,
                                             dl2);
-                else if (res)
+                else if (rres)
                     rows_dist<KT, RPT>(dense, P.dpad, x_l, off_l, cols_l, vals_l, pat, pairv, rr, vv, gl, lpr, nuu,
                                        nll, du2, dl2);
                 else
