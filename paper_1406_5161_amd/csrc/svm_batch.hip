@@ -319,6 +319,17 @@ DEV void team_write(unsigned long long* trec, int B, int rank, unsigned seq, con
     }
 }
 
+// Int sum over the wave by DPP (row sums, then rows 0-3 into lane 63), returned in every lane.
+DEV int wave_sum_i32_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_XOR1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_XOR2, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_ROR4, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_ROR8, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_BCAST15, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_BCAST31, 0xC, 0xF, false);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 DEV void pack_d(unsigned* v, int k, double x) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(x);
     v[k] = (unsigned)(b & 0xffffffffull);
@@ -361,7 +372,8 @@ DEV TeamSel team_select(const BatchDesc& P, int rank, unsigned seq, double bu, i
                 xc = (long long)(((unsigned long long)v[11] << 32) | v[10]);
             }
             const int myiu = xiu, myil = xil;
-            const long long tot = wave_sum(xc);
+            // active-row counts: the team's total is at most n < 2^31
+            const long long tot = wave_sum_i32_dpp((int)xc);
             wave_reduce_sel(xbu, xiu, xbl, xil);
             if (lane < P.team && myiu == xiu && xiu != IDX_NONE) sh.tsel[2] = xau;
             if (lane < P.team && myil == xil && xil != IDX_NONE) sh.tsel[3] = xal;
