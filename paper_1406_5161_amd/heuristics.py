@@ -6,7 +6,10 @@ iterations, reconstructions, shrink passes, samples shrunk, and the dual objecti
 to the unshrunk run (every run stops at the same 2 eps gap, so the duals agree to within the
 eps band, not exactly).
 
-    python -m paper_1406_5161_amd.heuristics --config 2
+    python -m paper_1406_5161_amd.heuristics --config 2 [--from K]
+
+--from K runs plain SMO (the reference of the dual column) and then grid entries K onwards
+(1 = the first shrinking heuristic), to complete a grid that an earlier run left unfinished.
 """
 from __future__ import annotations
 
@@ -25,7 +28,7 @@ for mode_name, mode in (("single", g.SHRINK_SINGLE), ("multi", g.SHRINK_MULTI)):
         GRID.append(("%s numsamples:%d%%" % (mode_name, round(frac * 100)), mode, g.KIND_FRACTION, frac))
 
 
-def run(config: int, log=print, repeats: int = 1) -> list:
+def run(config: int, log=print, repeats: int = 1, first: int = 1) -> list:
     import torch
     from . import svmhip as S
     cfg = g.CONFIGS[config]()
@@ -37,7 +40,7 @@ def run(config: int, log=print, repeats: int = 1) -> list:
     ws = torch.empty(S.svm_train_workspace_size(dp, base), dtype=torch.uint8, device="cuda")
     rc, _ = S.svm_train(dp, base, alpha, f, workspace=ws)   # warm-up
     rows, ref = [], None
-    for name, mode, kind, param in GRID:
+    for name, mode, kind, param in GRID[:1] + GRID[max(1, first):]:
         p = S.make_params(cfg.C, cfg.gamma, cfg.eps, mode, kind, param)
         best = None
         for _ in range(repeats):
@@ -66,8 +69,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--repeats", type=int, default=1)
+    ap.add_argument("--from", dest="first", type=int, default=1)
     a = ap.parse_args()
-    rows = run(a.config, log=lambda *x: print(*x, file=sys.stderr, flush=True), repeats=a.repeats)
+    rows = run(a.config, log=lambda *x: print(*x, file=sys.stderr, flush=True), repeats=a.repeats, first=a.first)
     print(json.dumps({"workload": g.CONFIGS[a.config]().name, "grid": rows}))
 
 
