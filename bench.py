@@ -91,6 +91,27 @@ def recon_summary(results, data):
     return rec
 
 
+def decision_summary(S, torch, dp, alpha, res, cfg, reps=3):
+    """svm_decision over the workload's held-out queries with the trained alpha: queries/s and
+    kernel values (query x support vector) per second, from the average of `reps` timed calls
+    on the current stream after one untimed call."""
+    q = S.to_device(cfg.queries, with_labels=False)
+    out = torch.zeros(cfg.queries.n, dtype=torch.float64, device="cuda")
+    rc = S.svm_decision(dp, alpha, res.beta, cfg.gamma, q, out)
+    assert rc == S.SVM_OK, S.strerror(rc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rc = S.svm_decision(dp, alpha, res.beta, cfg.gamma, q, out)
+        assert rc == S.SVM_OK, S.strerror(rc)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"queries": cfg.queries.n, "n_sv": res.n_sv, "ms_per_call": ms,
+            "queries_per_s": cfg.queries.n / (ms * 1e-3),
+            "kernel_values_per_s": cfg.queries.n * res.n_sv / (ms * 1e-3)}
+
+
 def cpu_baseline(cfg, iters):
     import numpy as np  # noqa: F401
     from oracle import oracle as O
@@ -206,6 +227,8 @@ def main():
                      "full_active_set_GBs": full_gbs},
     }
     out["reconstruction"] = recon_summary(results, data)
+    if cfg.queries is not None:
+        out["decision"] = decision_summary(S, torch, dp, alpha, last, cfg)
     if args.serve:
         out["serving"] = run_serve(args)
     if not args.no_cpu_baseline:
