@@ -331,6 +331,34 @@ def test_dense_kernel_sums_on_matrix_cores(S, d):
     assert err <= 1e-4
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_kernel_values_within_exp_error_bound(S, prec):
+    """Single kernel values K(x_s, q) = exp(-gamma d^2) through svm_decision with one unit
+    alpha.  Binary rows make d^2 an exact integer on both sides, so the only error left is the
+    exponential's.  FP32: gamma rounded to FP32, v = -gamma d^2 rounded, the product with
+    log2 e (itself rounded) and the hardware base-2 exponential (1 ulp; 2 allowed) bound
+    |K / exp(v) - 1| by (|v| + 1) 2^-22; the test allows twice that.  FP64: 1e-14 (|v| + 1)."""
+    cfg = sub(g.config2(), 600)
+    data = cfg.data
+    s = int(np.flatnonzero(data.y > 0)[0])
+    alpha = np.zeros(data.n)
+    alpha[s] = 1.0
+    q = cfg.queries.subset(np.arange(2000))
+    xs = data.to_dense()[s].astype(np.float64)
+    d2 = ((q.to_dense().astype(np.float64) - xs) ** 2).sum(axis=1)   # exact small integers
+    for gamma in (0.01, 0.1, 0.8):
+        v = -gamma * d2
+        keep = v > -80.0   # results stay normal FP32 numbers
+        dv = S.decision_data(data, alpha, 0.0, gamma, q, kernel_precision=prec)
+        rel = np.abs(dv[keep] / np.exp(v[keep]) - 1.0)
+        scale = np.abs(v[keep]) + 1.0
+        bound = scale * (2.0 ** -21 if prec == 0 else 1e-14)
+        P("prec", prec, "gamma", gamma, "rows", int(keep.sum()), "max rel err", rel.max(),
+          "max rel err / (|v| + 1)", (rel / scale).max())
+        assert keep.sum() > 1000
+        assert np.all(rel <= bound)
+
+
 # ------------------------------------------------------------------ warm start: one step from a given state
 
 def test_one_step_from_oracle_state(S):
