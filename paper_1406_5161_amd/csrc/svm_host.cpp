@@ -418,11 +418,14 @@ int train_impl(const svm_problem_t* p, const svm_params_t* q, double* alpha, dou
     const int max_mode = (q->flags & SVM_FLAG_NO_LDS_STATE) ? STEP_GLOBAL
                        : (q->flags & SVM_FLAG_NO_LDS_PAYLOAD) ? STEP_LDS_STATE : STEP_LDS_ALL;
     // Shape rules from per-phase timings of the loop on gfx950: one workgroup (no exchange at
-    // all) up to 4096 samples; beyond that about 800 samples per workgroup, at most 192
-    // workgroups (every workgroup reads every record, so the exchange grows with G^2).
+    // all) up to 4096 samples; beyond that about 700 samples per workgroup (at most 11 of the
+    // 16 waves hold a row, under three per SIMD), at most 224 workgroups (every workgroup reads
+    // every record, so the exchange grows with G^2).  Measured at the full active set: sparse
+    // binary n = 50,000 6.42 / 6.29 us per iteration at G = 63 / 72; dense n = 500,000
+    // 18.78 / 18.27 / 18.38 us at G = 192 / 224 / 256.
     const int cus = std::max(1, device_cu_count());
     int G = q->grid_blocks;
-    if (!G) G = p->n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 192), (p->n + 400) / 800));
+    if (!G) G = p->n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 224), (p->n + 350) / 700));
     G = std::min(G, p->n);
     const double avg_nnz = p->layout == SVM_CSR ? (double)hrp[p->n] / (double)p->n : 0.0;
     StepLds plan{};
