@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output directories (kernel traces and PMC counters).
 
     python -m paper_1406_5161_amd.profsum trace DIR [--kernel SUBSTR] [--last N]
-    python -m paper_1406_5161_amd.profsum pmc DIR [--kernel SUBSTR] [--last N]
+    python -m paper_1406_5161_amd.profsum pmc DIR [--kernel SUBSTR] [--last N] [--totals]
     python -m paper_1406_5161_amd.profsum traffic --fetch DIR --write DIR --calib-fetch DIR
         --calib-write DIR --calib-bytes B --kernel SUBSTR [--last N] [--source FILE ...]
         [--workload NAME] [--out JSON]
@@ -13,6 +13,8 @@ calls, total, average, minimum and maximum duration per kernel, and with
 --kernel the individual dispatch durations of the matching kernel (--last N:
 the statistics of its last N dispatches only).  `pmc` prints, per kernel and
 counter, the number of dispatches and the average value per dispatch.
+With --totals, `pmc` also adds up each counter over its hardware instances (one record per
+XCD or shader engine) and prints the per-dispatch totals of the --kernel dispatches.
 `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, one run each) of a
 kernel into HBM bytes per dispatch, each scaled by the factor that makes the
 same counter of the calibration copy (the copy kernel with the largest value in
@@ -120,6 +122,21 @@ def cmd_pmc(a):
             if a.last:
                 vals = vals[-a.last:]
             print("last %d: avg %.1f" % (len(vals), statistics.mean(vals)))
+    if a.kernel and a.totals:
+        tot = defaultdict(lambda: defaultdict(float))
+        inst = defaultdict(lambda: defaultdict(int))
+        for n, did, cn, v in cs:
+            if a.kernel in n:
+                tot[cn][did] += v
+                inst[cn][did] += 1
+        for cn in sorted(tot):
+            ds = sorted(tot[cn])
+            vals = [tot[cn][d] for d in ds]
+            print("\n*%s* %s total per dispatch (%d instances): %s" % (a.kernel, cn, inst[cn][ds[0]],
+                                                                      " ".join("%.6g" % v for v in vals)))
+            if a.last:
+                vals = vals[-a.last:]
+            print("last %d: avg %.6g" % (len(vals), statistics.mean(vals)))
 
 
 def source_hash(files):
@@ -180,6 +197,7 @@ def main():
     ap.add_argument("--calib-write")
     ap.add_argument("--calib-bytes", type=float)
     ap.add_argument("--source", nargs="*")
+    ap.add_argument("--totals", action="store_true")
     ap.add_argument("--out")
     ap.add_argument("--workload", default=None, help="name of the workload the counters were taken on")
     a = ap.parse_args()
