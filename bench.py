@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--serve-problems", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the method shards by samples; "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the method shards by samples; "
               "see the design notes), so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 

@@ -47,7 +47,7 @@ extern "C" {
 #define SVM_ENONFINITE (-3)      /* NaN or Inf in the sample values */
 #define SVM_EWORKSPACE (-4)      /* workspace too small or misaligned */
 #define SVM_EHIP (-5)            /* a HIP runtime call failed */
-#define SVM_EUNSUPPORTED (-6)    /* shape outside what this build handles (e.g. CSR row too long) */
+#define SVM_EUNSUPPORTED (-6)    /* shape outside what the library handles (e.g. CSR row too long) */
 #define SVM_ENOMEM (-7)          /* an internal allocation failed (server budget exhausted, ...) */
 #define SVM_EBUSY (-8)           /* serving: the ticket is still running */
 #define SVM_EABORT (-9)          /* the device loop stopped on its watchdog (barrier wait timed out) */

@@ -743,7 +743,7 @@ const char* svm_strerror(int code) {
         case SVM_ENONFINITE: return "NaN or Inf in the sample values";
         case SVM_EWORKSPACE: return "workspace too small or not 256-byte aligned";
         case SVM_EHIP: return hipGetErrorString(last_hip_error());
-        case SVM_EUNSUPPORTED: return "problem shape not supported by this build";
+        case SVM_EUNSUPPORTED: return "problem shape not supported by this library";
         case SVM_ENOMEM: return "device allocation failed or memory budget exhausted";
         case SVM_EBUSY: return "ticket still queued or running";
         case SVM_EABORT: return "device loop stopped by its barrier watchdog";
