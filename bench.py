@@ -26,7 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "smo_loop_cfg2_traffic.json")
+# committed HBM-counter summaries of the loop kernel, by workload
+PROFILE_COUNTERS = {
+    "cfg2_sparse_binary_n50000_d300": os.path.join(ROOT, "profiles", "smo_loop_cfg2_traffic.json"),
+    "cfg4_mixture_n500000_d28": os.path.join(ROOT, "profiles", "smo_loop_cfg4_traffic.json"),
+}
 
 
 def log(*a):
@@ -60,7 +64,7 @@ def traffic_from_profile(workload):
     """HBM bytes per loop launch from the committed counter summary, if it was taken on this
     workload and the loop kernel's sources have not changed since."""
     try:
-        prof = json.load(open(PROFILE_COUNTERS))
+        prof = json.load(open(PROFILE_COUNTERS.get(workload, "")))
     except Exception:
         return None
     if prof.get("kernel_source_sha256_16") != kernel_source_hash() or prof.get("workload") != workload:
