@@ -148,7 +148,13 @@ def source_hash(files):
 
 
 def _kernel_avg(d, counter, kernel, last):
-    vals = [v for n, _, cn, v in sorted(counters(d), key=lambda r: r[1]) if kernel in n and cn == counter]
+    """Average over the kernel's dispatches (the last `last`) of the counter's per-dispatch total
+    over its hardware instances."""
+    tot = defaultdict(float)
+    for n, did, cn, v in counters(d):
+        if kernel in n and cn == counter:
+            tot[did] += v
+    vals = [tot[k] for k in sorted(tot)]
     if last:
         vals = vals[-last:]
     if not vals:
