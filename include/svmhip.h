@@ -152,7 +152,8 @@ int svm_decision(const svm_problem_t* train, const double* alpha, double beta, d
  * solved by its own team of workgroups (one to 64: the smallest team whose
  * members can each keep their share of the samples, with its rows, in LDS,
  * when that share is at least 512 samples; else about 1500 samples per
- * workgroup; params[p].grid_blocks overrides), problems never synchronise
+ * workgroup, whose rows stream from HBM while their f, status and active
+ * list stay in LDS; params[p].grid_blocks overrides), problems never synchronise
  * with each other.  Every problem runs the whole method of svm_train (SMO
  * loop, shrinking, reconstruction, closing recompute) inside its team; alpha
  * and f do not depend on the team size or on the other problems.  alpha[p]
