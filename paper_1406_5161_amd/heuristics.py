@@ -6,10 +6,12 @@ iterations, reconstructions, shrink passes, samples shrunk, and the dual objecti
 to the unshrunk run (every run stops at the same 2 eps gap, so the duals agree to within the
 eps band, not exactly).
 
-    python -m paper_1406_5161_amd.heuristics --config 2 [--from K]
+    python -m paper_1406_5161_amd.heuristics --config 2 [--from K] [--max-seconds S]
 
 --from K runs plain SMO (the reference of the dual column) and then grid entries K onwards
 (1 = the first shrinking heuristic), to complete a grid that an earlier run left unfinished.
+--max-seconds S starts no further run once S seconds have passed, and still prints the
+record of the runs done (with the index to pass to --from).
 """
 from __future__ import annotations
 
@@ -28,7 +30,7 @@ for mode_name, mode in (("single", g.SHRINK_SINGLE), ("multi", g.SHRINK_MULTI)):
         GRID.append(("%s numsamples:%d%%" % (mode_name, round(frac * 100)), mode, g.KIND_FRACTION, frac))
 
 
-def run(config: int, log=print, repeats: int = 1, first: int = 1) -> list:
+def run(config: int, log=print, repeats: int = 1, first: int = 1, max_seconds: float = 0.0) -> list:
     import torch
     from . import svmhip as S
     cfg = g.CONFIGS[config]()
@@ -40,7 +42,12 @@ def run(config: int, log=print, repeats: int = 1, first: int = 1) -> list:
     ws = torch.empty(S.svm_train_workspace_size(dp, base), dtype=torch.uint8, device="cuda")
     rc, _ = S.svm_train(dp, base, alpha, f, workspace=ws)   # warm-up
     rows, ref = [], None
-    for name, mode, kind, param in GRID[:1] + GRID[max(1, first):]:
+    t_start = time.perf_counter()
+    entries = [(0, GRID[0])] + [(k, GRID[k]) for k in range(max(1, first), len(GRID))]
+    for idx, (name, mode, kind, param) in entries:
+        if max_seconds and rows and time.perf_counter() - t_start > max_seconds:
+            log("time limit: stopped before grid entry %d (%s); continue with --from %d" % (idx, name, idx))
+            break
         p = S.make_params(cfg.C, cfg.gamma, cfg.eps, mode, kind, param)
         best = None
         for _ in range(repeats):
@@ -70,8 +77,10 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--repeats", type=int, default=1)
     ap.add_argument("--from", dest="first", type=int, default=1)
+    ap.add_argument("--max-seconds", type=float, default=0.0)
     a = ap.parse_args()
-    rows = run(a.config, log=lambda *x: print(*x, file=sys.stderr, flush=True), repeats=a.repeats, first=a.first)
+    rows = run(a.config, log=lambda *x: print(*x, file=sys.stderr, flush=True), repeats=a.repeats, first=a.first,
+               max_seconds=a.max_seconds)
     print(json.dumps({"workload": g.CONFIGS[a.config]().name, "grid": rows}))
 
 
