@@ -197,7 +197,8 @@ def main():
     byts = sum(algorithmic_bytes(r, data) for r in results)
     achieved = byts / (loop_ms * 1e-3) / 1e9
     per_launch_bytes = byts / max(1, launches)
-    traffic = traffic_from_profile(cfg.name)
+    # the committed counter summaries were taken on the FP32-kernel-value loop
+    traffic = traffic_from_profile(cfg.name) if args.precision == "fp32" else None
 
     last = results[-1]
     out = {
