@@ -25,10 +25,30 @@ def build(force: bool = True) -> str:
     """Compile the oracle with plain gcc (-O2, no fast-math)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-fopenmp",
                                "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
+
+
+def _default_threads() -> int:
+    """ORACLE_THREADS if set, else every core this process may run on."""
+    v = os.environ.get("ORACLE_THREADS")
+    if v:
+        return max(1, int(v))
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
+
+def set_threads(t: int) -> int:
+    """Threads for the oracle's per-sample loops; results do not depend on it."""
+    return lib().orc_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return lib().orc_get_threads()
 
 
 class _Data(C.Structure):
@@ -82,7 +102,12 @@ def lib():
         L.orc_set_id.restype = C.c_int32
         L.orc_validate.argtypes = [P(_Data), P(_Params)]
         L.orc_validate.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
+        L.orc_get_threads.restype = C.c_int
+        L.orc_max_threads.restype = C.c_int
         _lib = L
+        L.orc_set_threads(_default_threads())
     return _lib
 
 

@@ -8,8 +8,12 @@
  * benchmark do.  It shares no code, header, table or constant generator with
  * the HIP library.
  *
- * Everything is double precision, single-threaded and written in the order of
- * the paper's equations, without blocking, fusion or reordering:
+ * Everything is double precision and written in the order of the paper's
+ * equations, without blocking, fusion or reordering.  Loops over samples whose
+ * iterations are independent (the f update, reconstruction, full recompute,
+ * classifier) may run on several OpenMP threads: each sample's own sum is still
+ * formed by one thread in the written order, so the results do not depend on
+ * the thread count (orc_set_threads; 1 = the plain single-threaded program):
  *
  *   kernel          K(a,b) = exp(-gamma * sum_k (a_k - b_k)^2)       Sec. "Datasets"
  *                   (gamma = 1/(2 sigma^2)); the squared distance is the
@@ -41,12 +45,24 @@
  * (alpha = 0, f = -y), not from the explicit initial pair of Alg. 1.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_TAU 1e-12        /* floor for eta = K_uu + K_ll - 2 K_ul */
 #define ORC_DELTA 1e-12      /* snap alpha to a bound within DELTA*C */
+#define ORC_PAR_MIN 4096     /* loops over fewer samples stay on one thread */
+
+static int orc_threads = 1;
+
+/* Threads for the per-sample loops (>= 1); returns the count in effect. */
+int orc_set_threads(int t) {
+    orc_threads = t < 1 ? 1 : t;
+    return orc_threads;
+}
+int orc_get_threads(void) { return orc_threads; }
+int orc_max_threads(void) { return omp_get_num_procs(); }
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_EINVAL = -1, ORC_EONECLASS = -2, ORC_ENONFINITE = -3,
        ORC_ENOMEM = -4 };
@@ -205,6 +221,7 @@ void orc_pair_update(double a_up, double a_low, int8_t y_up, int8_t y_low, doubl
 
 /* f_i = sum_j alpha_j y_j K_ij - y_i for every i (eq:fcache), increasing j. */
 void orc_f_full(const orc_data* X, const double* alpha, double gamma, double* f) {
+#pragma omp parallel for schedule(dynamic, 64) num_threads(orc_threads) if (X->n >= 64 && orc_threads > 1)
     for (int64_t i = 0; i < X->n; ++i) {
         double s = 0.0;
         for (int64_t j = 0; j < X->n; ++j)
@@ -220,16 +237,20 @@ double orc_dual(const orc_data* X, const double* alpha, double gamma) {
     double lin = 0.0;
     for (int64_t i = 0; i < X->n; ++i)
         if (alpha[i] > 0.0) { sv[m++] = (int32_t)i; lin += alpha[i]; }
-    double quad = 0.0;
+    double* g = (double*)malloc(sizeof(double) * (m > 0 ? m : 1));
+#pragma omp parallel for schedule(dynamic, 64) num_threads(orc_threads) if (m >= 64 && orc_threads > 1)
     for (int64_t a = 0; a < m; ++a) {
         int32_t i = sv[a];
-        double g = 0.0;
+        double s = 0.0;
         for (int64_t b = 0; b < m; ++b) {
             int32_t j = sv[b];
-            g += alpha[j] * (double)X->y[j] * orc_kernel(X, i, X, j, gamma);
+            s += alpha[j] * (double)X->y[j] * orc_kernel(X, i, X, j, gamma);
         }
-        quad += alpha[i] * (double)X->y[i] * g;
+        g[a] = s;
     }
+    double quad = 0.0;
+    for (int64_t a = 0; a < m; ++a) quad += alpha[sv[a]] * (double)X->y[sv[a]] * g[a];
+    free(g);
     free(sv);
     return lin - 0.5 * quad;
 }
@@ -237,6 +258,7 @@ double orc_dual(const orc_data* X, const double* alpha, double gamma) {
 /* Decision values sum_j alpha_j y_j K(x_j, z_q) - beta (eq:classi before sgn). */
 void orc_decision(const orc_data* X, const double* alpha, double beta, double gamma, const orc_data* Q,
                   double* out) {
+#pragma omp parallel for schedule(dynamic, 16) num_threads(orc_threads) if (Q->n >= 16 && orc_threads > 1)
     for (int64_t q = 0; q < Q->n; ++q) {
         double s = 0.0;
         for (int64_t j = 0; j < X->n; ++j)
@@ -282,6 +304,7 @@ int orc_validate(const orc_data* X, const orc_params* P) {
 /* Alg. 6: f of every sample outside the active set, from the current support vectors. */
 static void reconstruct(const orc_data* X, const double* alpha, double gamma, const uint8_t* active_mask,
                         double* f) {
+#pragma omp parallel for schedule(dynamic, 64) num_threads(orc_threads) if (X->n >= 64 && orc_threads > 1)
     for (int64_t i = 0; i < X->n; ++i) {
         if (active_mask[i]) continue;
         double s = 0.0;
@@ -340,6 +363,7 @@ int orc_train(const orc_data* X, const orc_params* P, double* alpha, double* f, 
             double du = nu - alpha[iu], dl = nl - alpha[il];
             double yu = (double)X->y[iu], yl = (double)X->y[il];
             /* f update over the active set (eq:fup) */
+#pragma omp parallel for schedule(static) num_threads(orc_threads) if (n_act >= ORC_PAR_MIN && orc_threads > 1)
             for (int64_t t = 0; t < n_act; ++t) {
                 int32_t i = act[t];
                 f[i] += yu * du * orc_kernel(X, iu, X, i, P->gamma) + yl * dl * orc_kernel(X, il, X, i, P->gamma);

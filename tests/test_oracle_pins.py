@@ -410,3 +410,97 @@ def test_validation_codes():
     assert O.validate(c) == O.OK
     c2 = g.SvmData("u", c.n, c.d, "csr", c.y, row_ptr=c.row_ptr, col=c.col[::-1].copy(), val=c.val)
     assert O.validate(c2) == O.EINVAL                 # unsorted columns
+
+
+# ------------------------------------------------------------------ degenerate pair, no free sample, threads
+
+def test_duplicate_rows_with_opposite_labels_take_the_eta_floor():
+    """Two identical rows with opposite labels: K_ul = 1, so eta = K_uu + K_ll - 2 K_ul = 0 and
+    the step runs with the floor tau (reading of eq:rho).  Along the constraint line the dual is
+    D = 2a, linear, so its maximum is the box end a1 = a2 = C (Platt's endpoint), reached in one
+    step; both samples are then bounded, I0 is empty, and beta = (b_up + b_low)/2 = 0 with
+    b_up = f_2 = +1 and b_low = f_1 = -1 (Sec. 3.1); D = 2C."""
+    x = np.array([[0.25, -1.5], [0.25, -1.5]], np.float32)
+    for C in (0.5, 3.0):
+        r = O.train(dense(x, [1, -1]), C, 0.7, eps=1e-9)
+        assert r.rc == 0 and r.iterations == 1
+        assert r.alpha[0] == C and r.alpha[1] == C
+        assert r.f[0] == -1.0 and r.f[1] == 1.0
+        assert r.b_up == 1.0 and r.b_low == -1.0
+        assert r.beta == 0.0
+        assert r.dual_obj == pytest.approx(2.0 * C, rel=1e-15)
+
+
+def test_beta_without_free_samples_is_the_threshold_midpoint():
+    """Every sample ends at a bound, so beta = (b_up + b_low)/2 (Sec. 3.1), in two layouts
+    whose thresholds are fixed by hand.
+    (a) The duplicate pair above plus a far sample x3 (y = +1, K with the pair exactly 0): the
+        pair goes to C, f3 = -1 stays in I1 and b_low = f1 = -1, so b_up = b_low = -1, beta = -1.
+    (b) The duplicate pair plus two far samples of opposite labels, far from each other as well,
+        with C = 0.5: after the pair, (x3, x4) is a pair with eta = 2 whose step 1 is clipped to
+        C, so every alpha is C; f = (-1, 1, C - 1, 1 - C), b_up = min(f2, f4) = 1 - C and
+        b_low = max(f1, f3) = C - 1, so beta = 0 while b_up = 0.5."""
+    far = 1.0e3
+    xa = np.array([[0.0, 0.0], [0.0, 0.0], [far, 0.0]], np.float32)
+    r = O.train(dense(xa, [1, -1, 1]), 2.0, 1.0, eps=1e-9)
+    assert r.rc == 0 and r.iterations == 1
+    np.testing.assert_array_equal(r.alpha, [2.0, 2.0, 0.0])
+    assert r.b_up == -1.0 and r.b_low == -1.0 and r.beta == -1.0
+    C = 0.5
+    xb = np.array([[0.0, 0.0], [0.0, 0.0], [far, 0.0], [0.0, far]], np.float32)
+    r = O.train(dense(xb, [1, -1, 1, -1]), C, 1.0, eps=1e-9)
+    assert r.rc == 0 and r.iterations == 2
+    np.testing.assert_array_equal(r.alpha, [C, C, C, C])
+    np.testing.assert_array_equal(r.f, [-1.0, 1.0, C - 1.0, 1.0 - C])
+    assert r.b_up == 1.0 - C and r.b_low == C - 1.0
+    assert r.beta == 0.0
+
+
+def test_duplicate_opposite_pair_inside_a_problem_reaches_the_qp_optimum():
+    """A tiny problem with one duplicated row carrying the other label (the eta floor is taken
+    whenever that pair is selected): at a tight eps the oracle reaches the optimum a general QP
+    solver (SciPy SLSQP) finds, for every shrinking mode."""
+    D = tiny_problem(9, 3, 21)
+    x = D.x.copy()
+    y = D.y.copy()
+    x[8] = x[3]
+    y[8] = -y[3]
+    D = dense(x, y)
+    X, yf = x.astype(np.float64), y.astype(np.float64)
+    C, gamma = 1.5, 0.5
+    Q = kmat(X, X, gamma) * np.outer(yf, yf)
+    res = minimize(lambda a: 0.5 * a @ Q @ a - a.sum(), np.zeros(9), jac=lambda a: Q @ a - 1.0,
+                   bounds=[(0, C)] * 9, constraints=[{"type": "eq", "fun": lambda a: yf @ a, "jac": lambda a: yf}],
+                   method="SLSQP", options={"ftol": 1e-15, "maxiter": 2000})
+    for mode, kind, param in [(0, 0, 0), (1, 0, 2), (2, 0, 2)]:
+        r = O.train(D, C, gamma, eps=1e-10, shrink_mode=mode, shrink_kind=kind, shrink_param=param)
+        assert r.rc == 0
+        Dr = dual_np(X, yf, r.alpha, gamma)
+        assert Dr >= -res.fun - 1e-9
+        assert Dr == pytest.approx(-res.fun, rel=1e-8)
+        assert r.alpha[3] == C and r.alpha[8] == C
+
+
+def test_thread_count_does_not_change_any_result():
+    """The per-sample loops may run on several threads; each sample's sum keeps its order, so
+    alpha, f, the trace and every scalar are bit-identical for 1 and 4 threads (a shrinking
+    solve large enough to take the threaded f update and reconstruction)."""
+    cfg = g.config2(n=4500, d=60, heuristic=(g.KIND_FIXED, 200.0))
+    old = O.get_threads()
+    try:
+        out = []
+        for t in (1, 4):
+            O.set_threads(t)
+            r = O.train_config(cfg, trace_cap=50_000)
+            q = cfg.queries.subset(np.arange(300))
+            head = cfg.data.subset(np.arange(800))
+            out.append((r, O.decision(cfg.data, r.alpha, r.beta, cfg.gamma, q),
+                        np.append(O.f_full(head, r.alpha[:800], cfg.gamma), O.dual(head, r.alpha[:800], cfg.gamma))))
+    finally:
+        O.set_threads(old)
+    (a, da, fa), (b, db, fb) = out
+    assert a.n_recon >= 1 and a.shrink_passes >= 1
+    assert a.iterations == b.iterations and a.dual_obj == b.dual_obj and a.beta == b.beta
+    assert np.array_equal(a.alpha, b.alpha) and np.array_equal(a.f, b.f)
+    assert np.array_equal(a.trace["i_up"], b.trace["i_up"]) and np.array_equal(a.trace["i_low"], b.trace["i_low"])
+    assert np.array_equal(da, db) and np.array_equal(fa, fb)
