@@ -1,19 +1,21 @@
 """Benchmark of the SMO trainer on one MI355X.
 
-A step is one full training solve (every part of the hot path: pair updates,
-f updates, two-threshold selection, shrinking with compaction, gradient
-reconstruction, closing recompute) of the sparse-binary workload:
-n = 50,000, d = 300, CSR at 12% density, values 1.0, Zipf(1.1) columns, labels
-from a sparse linear teacher with 10% flips; RBF gamma = 1/300, C = 1,
-eps = 1e-3, lazy shrinking (numsamples 50%) with multi reconstruction.  The
-inputs are resident in HBM before the timed region starts.
+A step is one full training solve to the KKT tolerance, with every part of the hot path:
+pair updates, f updates, two-threshold selection, shrinking with compaction, gradient
+reconstruction (on the matrix cores) and the closing recompute.  The default workload is the
+largest single-GPU configuration by bytes per SMO step, the text-like one: n = 200,000,
+d = 47,000 CSR with about 75 nonzeros per row (Zipf(1.1) columns, lognormal values, unit
+rows), labels from a sparse linear teacher with 5% flips; RBF gamma = 1, C = 4, eps = 1e-3,
+earliest shrinking (random:2) with multi reconstruction.  The inputs are resident in HBM
+before the timed region starts.
 
-Prints ONE JSON line.  ``value`` is SMO iterations per second over the timed
-solves; ``train_s`` is seconds to KKT at eps = 1e-3.  ``roofline`` is the SMO
-loop kernel's algorithmic bytes (rows and nonzeros it actually streamed, times
-the per-row / per-nonzero byte counts below) over its HIP-event-timed duration.
-``cpu_baseline`` is the FP64 oracle on the host cores on a bounded sample of the
-same solve.  ``--serve`` adds the batched / serving comparison.
+Prints ONE JSON line.  ``value`` is SMO iterations per second over the timed solves;
+``train_s`` is seconds to KKT at eps = 1e-3.  ``roofline`` is the SMO loop kernel's
+algorithmic bytes (rows and nonzeros it actually streamed, times the per-row / per-nonzero
+byte counts below) over its HIP-event-timed duration; ``reconstruction`` gives the kernel
+sums' matrix-core rate.  ``serving`` is the batched / serving comparison on the 256-problem
+Poisson stream (``--no-serve`` skips it).  ``cpu_baseline`` is the FP64 oracle on the host
+cores (all of them, and one) on a bounded sample of the same solve.
 """
 import argparse
 import hashlib
@@ -37,14 +39,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(res, data):
-    """Bytes one streaming pass must move per active row: CSR 4 B per nonzero (column id;
-    values skipped when all are 1.0, else 8 B with the value) + f read and write 16 + status 1
-    + active id 4 + row pointer 4 + norm 4 = 29 per row.  Dense: 4 B per feature + 25 per row."""
-    if data.layout == "csr":
-        per_nnz = 4 if res.pattern_only else 8
-        return per_nnz * res.nnz_streamed + 29 * res.rows_streamed
-    return (4 * data.d + 25) * res.rows_streamed
+def algorithmic_bytes(res, data, kbytes=4):
+    """Bytes the streaming passes must move: per active row visited, f read and write 16 +
+    status 1 + active id 4 + norm 4 = 25; per row whose data is read, CSR 4 B per nonzero
+    (column id; values skipped when all are 1.0, else 8 B with the value) + row pointer 4, or
+    dense 4 B per feature; per kernel value read from or written to the row cache, its size."""
+    payload = (4 if res.pattern_only else 8) * res.nnz_streamed + 4 * res.rows_read if data.layout == "csr" \
+        else 4 * data.d * res.rows_read
+    return payload + 25 * res.rows_streamed + kbytes * res.cache_values
 
 
 # sources of the SMO loop kernel, hashed in this order by the counter summary
@@ -73,25 +75,29 @@ def traffic_from_profile(workload):
 
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
+# kernel-row cache of the SMO loop per workload (MiB of the workspace), where rows stream from HBM
+DEFAULT_CACHE_MB = {}
 
 
 def recon_summary(results, data):
     """Reconstruction / closing-recompute kernel sums over the timed solves: (row, support
-    vector) pairs, their time, and for dense rows on the matrix cores the dot-product flops
-    (2 * dpad per pair) against the FP32 matrix peak."""
+    vector) pairs and their time; on the matrix cores, the dot-product flops per pair (2 * dpad
+    for dense rows, 2 * H for the dense head of wide CSR rows) against the FP32 matrix peak."""
     ms = sum(r.ms_ksum for r in results)
     pairs = sum(r.recon_pairs for r in results)
-    kern = ("kernel_sum_mfma_kernel" if results[-1].ksum_mfma
-            else "kernel_sum_bits_kernel" if data.layout == "csr" and results[-1].pattern_only and data.d <= 1024
+    last = results[-1]
+    kern = ("kernel_sum_mfma_kernel" if last.ksum_mfma == 1
+            else "kernel_sum_ht_kernel" if last.ksum_mfma == 2
+            else "kernel_sum_bits_kernel" if data.layout == "csr" and last.pattern_only and data.d <= 1024
             else "kernel_sum_slot_kernel" if data.layout == "csr" and data.d > 12288 else "kernel_sum_kernel")
     rec = {"kernel": kern,
            "ms_per_solve": ms / len(results), "pairs_per_solve": pairs / len(results),
            "pairs_per_s": pairs / (ms * 1e-3) if ms > 0 else None}
-    if results[-1].ksum_mfma:
-        dpad = (data.d + 3) // 4 * 4
-        tflops = 2.0 * dpad * pairs / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    if last.ksum_mfma:
+        k = (data.d + 3) // 4 * 4 if last.ksum_mfma == 1 else last.head_cols
+        tflops = 2.0 * k * pairs / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
         rec.update({"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": tflops / FP32_MFMA_PEAK_TFLOPS})
+                    "frac": tflops / FP32_MFMA_PEAK_TFLOPS, "k_per_pair": k})
     return rec
 
 
@@ -116,15 +122,50 @@ def decision_summary(S, torch, dp, alpha, res, cfg, reps=3):
             "kernel_values_per_s": cfg.queries.n * res.n_sv / (ms * 1e-3)}
 
 
-def cpu_baseline(cfg, iters):
-    import numpy as np  # noqa: F401
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def cpu_baseline(cfg, seconds):
+    """The oracle (FP64, as it stands) on the first iterations of the same solve, once on every
+    core this process may use and once on one thread: a short calibration run, then about
+    `seconds` of work per leg; iterations per second."""
     from oracle import oracle as O
-    t0 = time.perf_counter()
-    r = O.train_config(cfg, max_iter=iters)
-    dt = time.perf_counter() - t0
-    return {"value": r.iterations / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d SMO iterations of the same solve (full active set: the lazy schedule first "
-                      "shrinks after n/2 iterations), FP64, single thread, %.1f s" % (r.iterations, dt)}
+    model, cores = host_cpu()
+    legs = {}
+    old = O.get_threads()
+    try:
+        for label, threads in (("all_cores", cores), ("single_thread", 1)):
+            O.set_threads(threads)
+            t0 = time.perf_counter()
+            r = O.train_config(cfg, max_iter=8)
+            dt = time.perf_counter() - t0
+            k = int(max(8, min(50_000, 8 * seconds / max(dt, 1e-3))))
+            t0 = time.perf_counter()
+            r = O.train_config(cfg, max_iter=k)
+            dt = time.perf_counter() - t0
+            legs[label] = {"value": r.iterations / dt, "unit": "iters/s", "cores": threads,
+                           "iterations": r.iterations, "seconds": dt}
+            log("cpu baseline %s: %d iterations in %.1f s on %d threads" % (label, r.iterations, dt, threads))
+    finally:
+        O.set_threads(old)
+    main = legs["all_cores"]
+    return {"value": main["value"], "unit": "iters/s", "cores": main["cores"], "kind": "oracle",
+            "sample": "first %d SMO iterations of the same solve (FP64 oracle, %d threads, %.1f s; a capped "
+                      "exit reconstructs any shrunk samples)" % (main["iterations"], main["cores"], main["seconds"]),
+            "single_thread": legs["single_thread"], "host_cpu": model, "nproc": cores}
 
 
 def run_serve(args):
@@ -137,11 +178,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, help="workload: 2 (default), 1, 3 or 4")
+    ap.add_argument("--config", type=int, default=3, help="workload: 3 (default), 1, 2 or 4")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--cpu-iters", type=int, default=300)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle work per CPU-baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", action="store_true", help="also run the batched / serving comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the batched / serving comparison")
+    ap.add_argument("--cache-mb", type=int, default=-1,
+                    help="kernel-row cache of the SMO loop in MiB (-1: the workload's default, 0: none)")
     ap.add_argument("--serve-problems", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -160,7 +203,8 @@ def main():
     prec = S.SVM_KERNEL_FP32 if args.precision == "fp32" else S.SVM_KERNEL_FP64
     log("workload %s n=%d d=%d nnz=%d" % (cfg.name, data.n, data.d, data.nnz))
     dp = S.to_device(data)
-    params = S.params_for(cfg, kernel_precision=prec)
+    cache_mb = args.cache_mb if args.cache_mb >= 0 else DEFAULT_CACHE_MB.get(args.config, 0)
+    params = S.params_for(cfg, kernel_precision=prec, cache_mb=cache_mb)
     alpha = torch.zeros(data.n, dtype=torch.float64, device="cuda")
     f = torch.zeros(data.n, dtype=torch.float64, device="cuda")
     ws = torch.empty(S.svm_train_workspace_size(dp, params), dtype=torch.uint8, device="cuda")
@@ -177,7 +221,7 @@ def main():
     rc, r200 = S.svm_train(dp, p200, alpha, f, workspace=ws)
     assert rc in (S.SVM_OK, S.SVM_NOT_CONVERGED), S.strerror(rc)
     full_us = r200.ms_step * 1e3 / max(1, r200.iterations)
-    full_gbs = algorithmic_bytes(r200, data) / (r200.ms_step * 1e-3) / 1e9
+    full_gbs = algorithmic_bytes(r200, data, 8 if args.precision == 'fp64' else 4) / (r200.ms_step * 1e-3) / 1e9
 
     results = []
     torch.cuda.synchronize()
@@ -194,7 +238,7 @@ def main():
     iters = sum(r.iterations for r in results)
     loop_ms = sum(r.ms_step for r in results)
     launches = sum(r.n_launches for r in results)
-    byts = sum(algorithmic_bytes(r, data) for r in results)
+    byts = sum(algorithmic_bytes(r, data, 8 if args.precision == 'fp64' else 4) for r in results)
     achieved = byts / (loop_ms * 1e-3) / 1e9
     per_launch_bytes = byts / max(1, launches)
     # the committed counter summaries were taken on the FP32-kernel-value loop
@@ -218,11 +262,13 @@ def main():
                    "C": cfg.C, "gamma": cfg.gamma, "eps": cfg.eps, "shrink_mode": cfg.shrink_mode,
                    "shrink_kind": cfg.shrink_kind, "shrink_param": cfg.shrink_param,
                    "kernel_precision": args.precision, "f_dtype": "f64", "grid_blocks": last.grid_blocks,
-                   "lanes_per_row": last.lanes_per_row},
+                   "lanes_per_row": last.lanes_per_row, "head_cols": last.head_cols, "cache_mb": cache_mb,
+                   "cache_rows": last.cache_rows},
         "train_s": elapsed / args.steps,
         "iterations_per_solve": last.iterations,
         "n_sv": last.n_sv, "n_bsv": last.n_bsv, "n_recon": last.n_recon, "dual_obj": last.dual_obj,
         "loop_ms_per_solve": loop_ms / args.steps,
+        "cache_both_per_solve": last.cache_both, "rows_read_frac": last.rows_read / max(1, last.rows_streamed),
         "recon_ms_per_solve": sum(r.ms_recon for r in results) / args.steps,
         "us_per_iter_full_active": full_us,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -234,10 +280,10 @@ def main():
     out["reconstruction"] = recon_summary(results, data)
     if cfg.queries is not None:
         out["decision"] = decision_summary(S, torch, dp, alpha, last, cfg)
-    if args.serve:
+    if not args.no_serve:
         out["serving"] = run_serve(args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -100,8 +100,18 @@ typedef struct {
     int32_t kernel_precision; /* SVM_KERNEL_FP32 | SVM_KERNEL_FP64 */
     uint32_t flags;           /* SVM_FLAG_* */
     int32_t grid_blocks;      /* 0 = choose automatically; else the number of workgroups of the step
-                                 (svm_train) or of the problem's team (batch / server, at most 16) */
+                                 (svm_train) or of the problem's team (batch / server, at most 64) */
     int32_t lanes_per_row;    /* 0 = choose automatically; CSR lanes per row (1, 2, 4, 8, 16, 32, 64) */
+    int32_t head_cols;        /* CSR with d > 12,288 and FP32 kernel values (svm_train): columns kept as dense
+                                 rows for the matrix cores in the reconstruction and recompute sums (Alg. 6),
+                                 the most frequent ones; 0 = automatic (64), 32, 64 or 128; -1 = none (every
+                                 nonzero through the sparse path) */
+    int32_t cache_mb;         /* svm_train: MiB of the workspace for a kernel-row cache (0 = none).  Used when
+                                 the SMO loop streams rows from HBM (not for rows kept in LDS, not for binary
+                                 bitset rows): a slot holds K(s, i) of one sample s for every sample i, slot
+                                 s mod S for S = min(n, cache_mb MiB / (n * value bytes)) slots; an iteration
+                                 whose two pair rows are both in the cache reads no row data.  The cached values
+                                 are the ones the loop computes, so results are identical with and without it. */
 } svm_params_t;
 
 typedef struct {
@@ -123,9 +133,15 @@ typedef struct {
     int64_t nnz_streamed;     /* CSR: nonzeros of those rows (0 for dense) */
     int32_t pattern_only;     /* CSR values were all 1.0 and were not read */
     int32_t lanes_per_row;    /* CSR lanes per row used by the step */
-    int32_t ksum_mfma;        /* 1: reconstruction sums ran on the matrix cores (dense, FP32) */
+    int32_t ksum_mfma;        /* reconstruction sums on the matrix cores: 1 dense rows (FP32), 2 the dense head
+                                 of wide CSR rows (FP32), 0 none */
     double ms_ksum;           /* time in the reconstruction / recompute kernel-sum launches (HIP events) */
     int64_t recon_pairs;      /* (row, support vector) pairs those launches evaluated */
+    int32_t head_cols;        /* head columns of the wide-CSR kernel sums (0: not used) */
+    int32_t cache_rows;       /* slots of the kernel-row cache (0: not used) */
+    int64_t rows_read;        /* of rows_streamed, those whose row data was read (the rest came from the cache) */
+    int64_t cache_values;     /* kernel values read from or written to the row cache */
+    int64_t cache_both;       /* iterations whose two kernel rows both came from the cache */
 } svm_result_t;
 
 /* Bytes of device workspace svm_train needs for this problem (256-byte aligned). */
@@ -140,13 +156,40 @@ size_t svm_train_workspace_size(const svm_problem_t* prob, const svm_params_t* p
 int svm_train(const svm_problem_t* prob, const svm_params_t* params, double* alpha, double* f,
               svm_result_t* out, void* workspace, size_t ws_bytes, void* stream);
 
+/* Several training problems over one sample set, trained in lockstep: one-vs-rest labelings
+ * of a dataset or a C / gamma grid (the problems the paper's sample distribution shares, Sec.
+ * "Data Structure Organization").  Each SMO iteration (Alg. 2, eq:fup, eq:bminmax) advances
+ * every unconverged problem and reads each row once for all of them, so the row bytes per
+ * problem-iteration fall about k-fold.  x: the shared samples (its y is not used); y[p]: the
+ * labels of problem p (device, n bytes); params[p]: its C, gamma, eps, max_iter and flags,
+ * with shrink_mode SVM_SHRINK_NONE and one kernel_precision for all (SVM_EUNSUPPORTED
+ * otherwise); alpha[p] / f[p] (f may be NULL) and out[p] as in svm_train.  1 <= k <= 8; rows
+ * dense, or CSR whose values are all 1.0 with d <= 1024 (kept as bitsets); SVM_EUNSUPPORTED
+ * for other CSR.  Every problem's arithmetic is its svm_train run's (same trajectory, same
+ * closing recompute), so alpha and f equal those of svm_train with the same parameters bit for
+ * bit.  workspace: at least svm_train_shared_workspace_size() bytes, or NULL/0 to let the
+ * library allocate it.  out[p].ms_step and rows_streamed are those of the shared launches. */
+size_t svm_train_shared_workspace_size(const svm_problem_t* x, int32_t k, const int8_t* const* y,
+                                       const svm_params_t* params);
+int svm_train_shared(const svm_problem_t* x, int32_t k, const int8_t* const* y, const svm_params_t* params,
+                     double* const* alpha, double* const* f, svm_result_t* out, void* workspace, size_t ws_bytes,
+                     void* stream);
+
 /* Decision values out[q] = sum_j alpha_j y_j K(x_j, z_q) - beta (eq:classi
  * before the sign; the class is +1 when the value is >= 0).  train: the
  * training set (labels required); alpha: n doubles; queries: nq samples of
- * the same d (labels ignored); out: nq doubles.  kernel_precision as in
- * svm_params_t.  Allocates its scratch on `stream` (stream-ordered). */
+ * the same d and the same family of layout (dense or CSR; labels ignored);
+ * out: nq doubles.  kernel_precision as in svm_params_t.  workspace/ws_bytes:
+ * device scratch of at least svm_decision_workspace_size() bytes, 256-byte
+ * aligned (SVM_EWORKSPACE otherwise), or NULL/0 to let the library allocate
+ * and free it on `stream` (stream-ordered).  Binary CSR rows on both sides
+ * (every value 1.0, d <= 1024) are summed through bitsets; CSR with
+ * 12,288 < d <= 65,535 and FP32 kernel values through the dense head of the
+ * 64 most frequent training columns on the matrix cores plus the sparse tail. */
+size_t svm_decision_workspace_size(const svm_problem_t* train, const svm_problem_t* queries, int32_t kernel_precision);
 int svm_decision(const svm_problem_t* train, const double* alpha, double beta, double gamma,
-                 const svm_problem_t* queries, double* out, int32_t kernel_precision, void* stream);
+                 const svm_problem_t* queries, double* out, int32_t kernel_precision, void* workspace,
+                 size_t ws_bytes, void* stream);
 
 /* Several independent problems in one persistent fused launch: problem p is
  * solved by its own team of workgroups (one to 64: the smallest team whose

@@ -47,7 +47,8 @@ struct Ctl {
     int32_t err;              // validation error bits
     int32_t n_pos, n_neg;
     int32_t max_row_nnz;
-    int32_t pad[4];
+    int32_t pad0;
+    int64_t cache_both;       // iterations whose two kernel rows both came from the row cache
 };
 static_assert(sizeof(Ctl) <= 256, "Ctl must fit in its slot");
 
@@ -88,7 +89,8 @@ struct StepArgs {
     double* tr_bu;
     double* tr_bl;
     unsigned long long spin_limit;  // watchdog for one barrier wait (wall-clock ticks)
-    unsigned long long* work;       // [G][2]: rows and nonzeros streamed by each workgroup in this launch
+    unsigned long long* work;       // [G][4] per workgroup in this launch: active rows visited, nonzeros read,
+                                    // rows whose payload was read, kernel-row cache values read or written
     // where each workgroup keeps its segment during a launch
     int32_t mode;             // STEP_GLOBAL, STEP_LDS_STATE or STEP_LDS_ALL
     int32_t nseg_max;         // rows of the largest segment
@@ -100,6 +102,13 @@ struct StepArgs {
     const uint32_t* bits;     // LAY_BITS: rows as bitsets [n][wpr]
     int32_t wpr;
     int32_t pad3;
+    // kernel-row cache (rows streamed from HBM): slot s of `cache` holds K(id, i) for the
+    // samples i of every segment, id being the sample named by the workgroup's own tag of slot
+    // s; a slot holds sample id % cache_rows.  Values are KT; tags are epoch << 32 | id.
+    void* cache;              // [cache_rows][n], or NULL
+    unsigned long long* tags; // [G][cache_rows]
+    int32_t cache_rows;
+    uint32_t epoch;           // tag epoch of this launch (> 0; the host zeroes the tags per solve)
 };
 
 // Residency of a workgroup's segment during one launch of the SMO loop:
@@ -163,7 +172,8 @@ hipError_t launch_reset_active(int n, int G, int32_t* seg_start, int32_t* cnt, i
 hipError_t launch_select(int G, const int32_t* seg_start, const int32_t* cnt, const int32_t* act, const double* f,
                          const double* alpha, const int8_t* y, double C, Rec* rec, Ctl* ctl, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, size_t lds, hipStream_t s);
-int step_max_blocks(int lay, int lpr, int kprec, int mode, size_t lds);
+int step_max_blocks(int lay, int lpr, int kprec, int mode, size_t lds, bool cache);
+bool step_cache_capable(int lay, int mode);   // layouts and residencies with a kernel-row cache
 hipError_t launch_mark_active(int n, int G, const int32_t* seg_start, const int32_t* cnt, const int32_t* act,
                               uint8_t* mask, hipStream_t s);
 // stable compaction: list = ascending ids i with pred(i); pred: 0 = mask[i]==0, 1 = alpha[i] > 0, 2 = all
@@ -183,6 +193,86 @@ hipError_t launch_summary(int n, const double* alpha, const double* f, const int
 hipError_t launch_check_pattern(int nnz, const float* val, int32_t* flag, hipStream_t s);
 
 int device_cu_count();
+
+// ---- wide CSR kernel sums with the frequent columns as dense rows (svm_ksum_ht.hip)
+constexpr int HT_BLOCK = 512;         // threads per workgroup
+constexpr int HT_CHUNK = 64;          // support vectors per sweep step
+constexpr int HT_TILE_MAX = 64;       // target rows per workgroup (16, 32 or 64)
+constexpr int HT_ENTRIES = 4096;      // tail nonzeros of one tile of target rows (LDS table)
+constexpr int HT_SLOTS = 8192;        // LDS hash slots for their columns
+constexpr int HT_MAX_D = 65535;       // column ids fit the hash key
+constexpr int HT_MAX_WORDS = (HT_MAX_D + 32) / 32;   // head-column bitmap words
+constexpr int HT_H_MAX = 128;         // head columns: 32, 64 or 128
+constexpr int HT_H_DEFAULT = 64;
+
+struct HtArgs {
+    int32_t H, d, na, nb;
+    int32_t tile_rows, nsplit;
+    // target rows (A): head rows [.][H], CSR for the tail, |x|^2
+    const float* a_head;
+    const int32_t* a_rp;
+    const int32_t* a_col;
+    const float* a_val;
+    const float* a_nrm;
+    const int32_t* alist;     // rows of A to evaluate (na), or NULL for 0..na-1
+    // support vectors (B), packed in sweep order by launch_ht_pack
+    const float* b_head;      // [nbp][H], nbp = nb rounded up to HT_CHUNK (zero rows beyond nb)
+    const float* b_nrm;       // [nbp]
+    const int32_t* b_toff;    // [nb + 1] tail offsets
+    const uint2* b_tent;      // tail nonzeros: (column << 6 | ordinal % 64, value bits)
+    const double* coef;       // [nb]
+    const uint32_t* hbits;    // head columns as a bitmap of (d + 31) / 32 words
+    double gamma;
+    double fx_scale, fx_inv;  // tail dots in 64-bit fixed point: value * fx_scale (a power of two)
+    double* part;             // [nsplit][na] partial sums
+};
+hipError_t launch_col_count(int64_t nnz, const int32_t* col, int32_t* cnt, hipStream_t s);
+hipError_t launch_ht_split(int n, int H, const int32_t* rp, const int32_t* col, const float* val,
+                           const int32_t* hmap, float* head, float* nrm, int32_t* tcnt, unsigned* maxn2,
+                           hipStream_t s);
+hipError_t launch_ht_tiles(int na, const int32_t* alist, const int32_t* tcnt, int32_t* out3, hipStream_t s);
+hipError_t launch_ht_pack(int nb, int H, const int32_t* blist, const float* head, const float* nrm, const int32_t* rp,
+                          const int32_t* col, const float* val, const int32_t* hmap, const int32_t* tcnt,
+                          int32_t* toff, float* bhead, float* bnrm, uint2* tent, hipStream_t s);
+hipError_t launch_kernel_sum_ht(const HtArgs& a, hipStream_t s);
+size_t ht_lds_bytes(int H);
+
+// ---- several problems over one sample set in lockstep (svm_shared.hip)
+constexpr int SHARED_MAX = 8;         // problems per launch
+constexpr int SHARED_BLOCK = 512;     // threads per workgroup
+constexpr int SHARED_GRID_MAX = 64;   // one wave merges a problem's records
+
+struct SharedProb {
+    const int8_t* y;
+    double* alpha;
+    double* f;
+    uint8_t* status;
+    Ctl* ctl;                 // state the launch starts from and ends with
+    double C, gamma, thr;
+    int64_t max_iter;
+};
+struct SharedArgs {
+    int32_t n, d, dpad, lay;  // lay: LAY_DENSE or LAY_BITS
+    int32_t wpr, k;           // bitset words per row; problems
+    int32_t live_mask;        // problems this launch advances (bit p)
+    int32_t pad;
+    const float* x;           // dense rows [n][dpad]
+    const uint32_t* bits;     // bitset rows [n][wpr]
+    Rec* rec;                 // [2][SHARED_MAX][G] exchange records, zeroed before the launch
+    unsigned long long spin_limit;
+    unsigned long long* work; // [G]: rows read by each workgroup (once per iteration for all problems)
+    SharedProb prob[SHARED_MAX];
+};
+hipError_t launch_shared(const SharedArgs& a, int G, int kprec, hipStream_t s);
+int shared_max_blocks(int lay, int kprec, size_t lds);
+size_t shared_lds_bytes(int lay, int d);
+
+// svm_decision on a caller-given device workspace (svm_host.cpp); *need receives the bytes the
+// problem needs (SVM_EWORKSPACE when ws_bytes is smaller).
+int decision_in_workspace(const svm_problem_t* train, const double* alpha, double beta, double gamma,
+                          const svm_problem_t* queries, double* out, int kprec, void* ws, size_t ws_bytes,
+                          hipStream_t s, size_t* need);
+void set_last_hip_error(hipError_t e);   // reported by svm_strerror(SVM_EHIP)
 
 }  // namespace svm
 

@@ -78,7 +78,7 @@ StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, l
     return p;
 }
 
-template <int LAY, typename KT, int LPR, int MODE>
+template <int LAY, typename KT, int LPR, int MODE, bool CACHE>
 __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     constexpr int BLOCK = STEP_BLOCK;
     constexpr int NW = BLOCK / 64;
@@ -94,6 +94,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     __shared__ int s_seli[3];
     __shared__ int s_prev_n;
     __shared__ unsigned long long s_ext[2];
+    __shared__ int s_cache[4];       // kernel-row cache: slot of i_up, slot of i_low, hit up, hit low
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int g = tid / LPR, gl = tid % LPR;
@@ -183,7 +184,9 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     long long iter = ctl->iter, counter = ctl->counter, n_act_total = ctl->n_active;
     long long passes = ctl->shrink_passes, shrunk = ctl->shrunk_total;
     int exit_reason = EXIT_NONE;
-    unsigned long long work_rows = 0, work_nnz = 0;
+    unsigned long long work_rows = 0, work_nnz = 0, work_payload = 0, work_cache = 0;   // payload, cache: CACHE only
+    long long cache_both = 0;
+    if constexpr (CACHE) cache_both = ctl->cache_both;
     // per-phase timer of workgroup 0, kept in LDS so it costs no registers
     __shared__ unsigned long long s_pt[PROF_SLOTS + 1];
     const bool prof_on = A.prof != nullptr && blk == 0 && tid == 0;
@@ -337,8 +340,28 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                 }
             }
         }
+        if constexpr (CACHE) {
+            // kernel rows of the pair from the cache: this workgroup's tags name the sample whose
+            // row (over this segment) each slot holds
+            if (tid == 0) {
+                const int S = A.cache_rows;
+                const int su = iu % S, sl = il % S;
+                const unsigned long long* tg = A.tags + (size_t)blk * S;
+                const unsigned long long ep = (unsigned long long)A.epoch << 32;
+                s_cache[0] = su;
+                s_cache[1] = sl;
+                s_cache[2] = ld_agent(tg + su) == (ep | (unsigned)iu);
+                s_cache[3] = ld_agent(tg + sl) == (ep | (unsigned)il);
+            }
+        }
         __syncthreads();
         const PairNew pn = pair_update(au, al, yu, yl, bu, bl, s_pair[0], C);
+        // kernel-row cache of this iteration: hits, and which missing rows get stored (when both
+        // rows map to one slot, only the up row may take it)
+        const int c_su = CACHE ? s_cache[0] : 0, c_sl = CACHE ? s_cache[1] : 0;
+        const bool c_hu = CACHE && s_cache[2], c_hl = CACHE && s_cache[3];
+        const bool c_stu = CACHE && !c_hu, c_stl = CACHE && !c_hl && c_sl != c_su;
+        const bool need_row = !(c_hu && c_hl);
         const KT gam = (KT)A.gamma;
         const KT nuu = (CSR || BITS) ? (KT)s_pair[1] : (KT)0, nll = (CSR || BITS) ? (KT)s_pair[2] : (KT)0;
 
@@ -354,14 +377,80 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         int ciu = IDX_NONE, cil = IDX_NONE;
         int newcount = 0;
         work_rows += (unsigned long long)nrows;
-        for (int base = 0; base < nrows; base += NG) {
+        if constexpr (CACHE) {
+            if (need_row) work_payload += (unsigned long long)nrows;
+            work_cache += (unsigned long long)nrows * ((int)c_hu + (int)c_hl + (int)c_stu + (int)c_stl);
+        }
+        // f update (eq:fup), the pair's alpha and status, the shrink rule and the candidates of
+        // one active row; returns whether the row stays active
+        auto update_row = [&](int li, int i, double ku, double kl) -> bool {
+            double fi;
+            {
+#pragma clang fp contract(off)
+                fi = F[li] + (pn.cu * ku + pn.cl * kl);
+            }
+            F[li] = fi;
+            uint8_t st = ST[li];
+            if (i == iu) {
+                st = st_make(yu > 0, pn.au, C);
+                ST[li] = st;
+                if constexpr (MODE == STEP_GLOBAL) st_agent(A.alpha + i, pn.au);
+                else AL[li] = pn.au;
+            } else if (i == il) {
+                st = st_make(yl > 0, pn.al, C);
+                ST[li] = st;
+                if constexpr (MODE == STEP_GLOBAL) st_agent(A.alpha + i, pn.al);
+                else AL[li] = pn.al;
+            }
+            const bool keep = !(do_shrink && shrink_rule(st, fi, bu, bl));
+            if (keep) {
+                if (st_in_up(st) && better_up(fi, i, cbu, ciu)) { cbu = fi; ciu = i; }
+                if (st_in_low(st) && better_low(fi, i, cbl, cil)) { cbl = fi; cil = i; }
+            }
+            return keep;
+        };
+        // stable in-place compaction of one chunk of the active list (every thread calls it)
+        auto compact = [&](bool keep, int li, int i) {
+            const unsigned long long m = __ballot(keep);
+            const int wpre = __popcll(m & ((1ull << lane) - 1ull));
+            if (lane == 0) s_wc[wid] = __popcll(m);
+            __syncthreads();
+            int off = 0, tot = 0;
+            for (int w = 0; w < NW; ++w) {
+                int c = s_wc[w];
+                off += (w < wid) ? c : 0;
+                tot += c;
+            }
+            if (keep) L[newcount + off + wpre] = (MODE == STEP_GLOBAL) ? i : li;
+            newcount += tot;
+            __syncthreads();
+        };
+        bool rows_done = false;
+        if constexpr (CACHE) {
+            if (!need_row) {
+                // both kernel rows come from the cache: no row data, one thread per active row
+                const KT* cu = reinterpret_cast<const KT*>(A.cache) + (size_t)c_su * A.n;
+                const KT* cl = reinterpret_cast<const KT*>(A.cache) + (size_t)c_sl * A.n;
+                for (int base = 0; base < nrows; base += BLOCK) {
+                    const int t = base + tid;
+                    const bool valid = t < nrows;
+                    const int li = valid ? (MODE == STEP_GLOBAL ? L[t] - seg0 : L[t]) : 0;
+                    const int i = seg0 + li;
+                    bool keep = false;
+                    if (valid) keep = update_row(li, i, (double)cu[i], (double)cl[i]);
+                    if (do_shrink) compact(keep, li, i);
+                }
+                rows_done = true;
+            }
+        }
+        for (int base = 0; base < (rows_done ? 0 : nrows); base += NG) {
             const int t = base + g;
             const bool valid = t < nrows;
             const int li = valid ? (MODE == STEP_GLOBAL ? L[t] - seg0 : L[t]) : 0;
             const int i = seg0 + li;
             bool keep = false;
             if (valid) {
-                KT du2, dl2;
+                KT du2 = (KT)0, dl2 = (KT)0;
                 if constexpr (LAY == LAY_DENSE) {
                     const float* xr = (MODE == STEP_LDS_ALL) ? XL + (size_t)li * A.dpad : A.x + (size_t)i * A.dpad;
                     dense_dist<KT>(xr, pairv, A.dpad, du2, dl2);
@@ -438,50 +527,34 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     if (dl2 < (KT)0) dl2 = (KT)0;
                 }
                 if (gl == 0) {
-                    const double ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2);
-                    const double kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2);
-                    double fi;
-                    {
-#pragma clang fp contract(off)
-                        fi = F[li] + (pn.cu * ku + pn.cl * kl);
+                    double ku, kl;
+                    if constexpr (CACHE) {
+                        KT* cv = reinterpret_cast<KT*>(A.cache);
+                        KT* cu = cv + (size_t)c_su * A.n + i;
+                        KT* cl = cv + (size_t)c_sl * A.n + i;
+                        ku = c_hu ? (double)*cu : (i == iu) ? 1.0 : (double)kexp(-gam * du2);
+                        kl = c_hl ? (double)*cl : (i == il) ? 1.0 : (double)kexp(-gam * dl2);
+                        if (c_stu) *cu = (KT)ku;
+                        if (c_stl) *cl = (KT)kl;
+                    } else {
+                        ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2);
+                        kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2);
                     }
-                    F[li] = fi;
-                    uint8_t st = ST[li];
-                    if (i == iu) {
-                        st = st_make(yu > 0, pn.au, C);
-                        ST[li] = st;
-                        if constexpr (MODE == STEP_GLOBAL) st_agent(A.alpha + i, pn.au);
-                        else AL[li] = pn.au;
-                    } else if (i == il) {
-                        st = st_make(yl > 0, pn.al, C);
-                        ST[li] = st;
-                        if constexpr (MODE == STEP_GLOBAL) st_agent(A.alpha + i, pn.al);
-                        else AL[li] = pn.al;
-                    }
-                    keep = !(do_shrink && shrink_rule(st, fi, bu, bl));
-                    if (keep) {
-                        if (st_in_up(st) && better_up(fi, i, cbu, ciu)) { cbu = fi; ciu = i; }
-                        if (st_in_low(st) && better_low(fi, i, cbl, cil)) { cbl = fi; cil = i; }
-                    }
+                    keep = update_row(li, i, ku, kl);
                 }
             }
-            if (do_shrink) {   // stable in-place compaction of this chunk of the active list
-                const unsigned long long m = __ballot(keep);
-                const int wpre = __popcll(m & ((1ull << lane) - 1ull));
-                if (lane == 0) s_wc[wid] = __popcll(m);
-                __syncthreads();
-                int off = 0, tot = 0;
-                for (int w = 0; w < NW; ++w) {
-                    int c = s_wc[w];
-                    off += (w < wid) ? c : 0;
-                    tot += c;
-                }
-                if (keep) L[newcount + off + wpre] = (MODE == STEP_GLOBAL) ? i : li;
-                newcount += tot;
-                __syncthreads();
-            }
+            if (do_shrink) compact(keep, li, i);
         }
         if (do_shrink) nrows = newcount;
+        if constexpr (CACHE) {
+            if (tid == 0) {
+                unsigned long long* tg = A.tags + (size_t)A.cache_rows * blk;
+                const unsigned long long ep = (unsigned long long)A.epoch << 32;
+                if (c_stu) st_agent(tg + c_su, ep | (unsigned)iu);
+                if (c_stl) st_agent(tg + c_sl, ep | (unsigned)il);
+                if (c_hu && c_hl) ++cache_both;
+            }
+        }
         lap(1);
 
         block_reduce_sel_wave0<BLOCK>(cbu, ciu, cbl, cil, s_v, s_i);   // wave 0 publishes
@@ -688,8 +761,10 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         if (tid == 0) {
             unsigned long long t = 0;
             for (int w = 0; w < NW; ++w) t += (unsigned long long)__double_as_longlong(s_v[w]);
-            A.work[2 * blk] = work_rows;
-            A.work[2 * blk + 1] = t;
+            A.work[4 * blk] = work_rows;
+            A.work[4 * blk + 1] = t;
+            A.work[4 * blk + 2] = CACHE ? work_payload : work_rows;
+            A.work[4 * blk + 3] = work_cache;
         }
     }
     if (prof_on) {
@@ -701,55 +776,61 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         ctl->a_up = au; ctl->a_low = al;
         ctl->iter = iter; ctl->counter = counter; ctl->n_active = n_act_total;
         ctl->shrink_passes = passes; ctl->shrunk_total = shrunk;
+        if constexpr (CACHE) ctl->cache_both = cache_both;
         ctl->exit_reason = exit_reason;
     }
 }
 
 // ------------------------------------------------------------------ dispatch
 
+bool step_cache_capable(int lay, int mode) { return lay != LAY_BITS && mode != STEP_LDS_ALL; }
+
 template <int LAY, typename KT, int LPR, int MODE>
-static const void* loop_fn() {
-    return (const void*)smo_loop_kernel<LAY, KT, LPR, MODE>;
+static const void* loop_fn(bool cache) {
+    if constexpr (LAY != LAY_BITS && MODE != STEP_LDS_ALL) {
+        if (cache) return (const void*)smo_loop_kernel<LAY, KT, LPR, MODE, true>;
+    }
+    return (const void*)smo_loop_kernel<LAY, KT, LPR, MODE, false>;
 }
 
 template <int LAY, typename KT, int MODE>
-static const void* pick_lpr(int lpr) {
+static const void* pick_lpr(int lpr, bool cache) {
     if constexpr (LAY == LAY_DENSE || LAY == LAY_BITS) {
-        return loop_fn<LAY, KT, 1, MODE>();
+        return loop_fn<LAY, KT, 1, MODE>(cache);
     } else {
         switch (lpr) {
-            case 1: return loop_fn<LAY, KT, 1, MODE>();
-            case 2: return loop_fn<LAY, KT, 2, MODE>();
-            case 4: return loop_fn<LAY, KT, 4, MODE>();
-            case 8: return loop_fn<LAY, KT, 8, MODE>();
-            case 16: return loop_fn<LAY, KT, 16, MODE>();
-            default: return loop_fn<LAY, KT, 32, MODE>();
+            case 1: return loop_fn<LAY, KT, 1, MODE>(cache);
+            case 2: return loop_fn<LAY, KT, 2, MODE>(cache);
+            case 4: return loop_fn<LAY, KT, 4, MODE>(cache);
+            case 8: return loop_fn<LAY, KT, 8, MODE>(cache);
+            case 16: return loop_fn<LAY, KT, 16, MODE>(cache);
+            default: return loop_fn<LAY, KT, 32, MODE>(cache);
         }
     }
 }
 
 template <int LAY, typename KT>
-static const void* pick_mode(int mode, int lpr) {
-    if (mode == STEP_LDS_ALL) return pick_lpr<LAY, KT, STEP_LDS_ALL>(lpr);
-    if (mode == STEP_LDS_STATE) return pick_lpr<LAY, KT, STEP_LDS_STATE>(lpr);
-    return pick_lpr<LAY, KT, STEP_GLOBAL>(lpr);
+static const void* pick_mode(int mode, int lpr, bool cache) {
+    if (mode == STEP_LDS_ALL) return pick_lpr<LAY, KT, STEP_LDS_ALL>(lpr, false);
+    if (mode == STEP_LDS_STATE) return pick_lpr<LAY, KT, STEP_LDS_STATE>(lpr, cache);
+    return pick_lpr<LAY, KT, STEP_GLOBAL>(lpr, cache);
 }
 
-static const void* pick(int lay, int kprec, int mode, int lpr) {
+static const void* pick(int lay, int kprec, int mode, int lpr, bool cache) {
     if (kprec == SVM_KERNEL_FP64) {
-        if (lay == LAY_DENSE) return pick_mode<LAY_DENSE, double>(mode, lpr);
-        if (lay == LAY_BITS) return pick_mode<LAY_BITS, double>(mode, lpr);
-        if (lay == LAY_CSR_TABLE) return pick_mode<LAY_CSR_TABLE, double>(mode, lpr);
-        return pick_mode<LAY_CSR_SLOT, double>(mode, lpr);
+        if (lay == LAY_DENSE) return pick_mode<LAY_DENSE, double>(mode, lpr, cache);
+        if (lay == LAY_BITS) return pick_mode<LAY_BITS, double>(mode, lpr, false);
+        if (lay == LAY_CSR_TABLE) return pick_mode<LAY_CSR_TABLE, double>(mode, lpr, cache);
+        return pick_mode<LAY_CSR_SLOT, double>(mode, lpr, cache);
     }
-    if (lay == LAY_DENSE) return pick_mode<LAY_DENSE, float>(mode, lpr);
-    if (lay == LAY_BITS) return pick_mode<LAY_BITS, float>(mode, lpr);
-    if (lay == LAY_CSR_TABLE) return pick_mode<LAY_CSR_TABLE, float>(mode, lpr);
-    return pick_mode<LAY_CSR_SLOT, float>(mode, lpr);
+    if (lay == LAY_DENSE) return pick_mode<LAY_DENSE, float>(mode, lpr, cache);
+    if (lay == LAY_BITS) return pick_mode<LAY_BITS, float>(mode, lpr, false);
+    if (lay == LAY_CSR_TABLE) return pick_mode<LAY_CSR_TABLE, float>(mode, lpr, cache);
+    return pick_mode<LAY_CSR_SLOT, float>(mode, lpr, cache);
 }
 
 hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, size_t lds, hipStream_t s) {
-    const void* fn = pick(a.lay, kprec, a.mode, lpr);
+    const void* fn = pick(a.lay, kprec, a.mode, lpr, a.cache != nullptr);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -759,8 +840,8 @@ hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, size_t lds,
     return hipLaunchCooperativeKernel(fn, dim3(G), dim3(STEP_BLOCK), args, (unsigned)lds, s);
 }
 
-int step_max_blocks(int lay, int lpr, int kprec, int mode, size_t lds) {
-    const void* fn = pick(lay, kprec, mode, lpr);
+int step_max_blocks(int lay, int lpr, int kprec, int mode, size_t lds, bool cache) {
+    const void* fn = pick(lay, kprec, mode, lpr, cache);
     if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, STEP_BLOCK, lds) != hipSuccess) return 0;

@@ -21,9 +21,11 @@ SVM_EUNSUPPORTED, SVM_ENOMEM, SVM_EBUSY, SVM_EABORT = -6, -7, -8, -9
 SVM_DENSE_ROW_MAJOR, SVM_DENSE_FEATURE_MAJOR, SVM_CSR = 0, 1, 2
 SVM_KERNEL_FP32, SVM_KERNEL_FP64 = 0, 1
 SVM_FLAG_WARM_START, SVM_FLAG_NO_FINAL_RECOMPUTE = 1, 2
-SVM_FLAG_NO_LDS_PAYLOAD, SVM_FLAG_NO_LDS_STATE = 4, 8
+SVM_FLAG_NO_LDS_PAYLOAD, SVM_FLAG_NO_LDS_STATE, SVM_FLAG_NO_BITSETS = 4, 8, 16
 
-EXPORTS = ["svm_train_workspace_size", "svm_train", "svm_decision", "svm_train_batch", "svm_server_create",
+EXPORTS = ["svm_train_workspace_size", "svm_train", "svm_train_shared_workspace_size", "svm_train_shared",
+           "svm_decision_workspace_size", "svm_decision",
+           "svm_train_batch", "svm_server_create",
            "svm_server_submit", "svm_server_poll", "svm_server_drain", "svm_server_stats", "svm_server_destroy",
            "svm_strerror", "svm_version", "svm_debug_select", "svm_debug_set_trace", "svm_debug_set_profile",
            "svm_debug_step_info"]
@@ -39,7 +41,7 @@ class svm_params_t(C.Structure):
     _fields_ = [("C", C.c_double), ("gamma", C.c_double), ("eps", C.c_double), ("shrink_mode", C.c_int32),
                 ("shrink_kind", C.c_int32), ("shrink_param", C.c_double), ("max_iter", C.c_int64),
                 ("kernel_precision", C.c_int32), ("flags", C.c_uint32), ("grid_blocks", C.c_int32),
-                ("lanes_per_row", C.c_int32)]
+                ("lanes_per_row", C.c_int32), ("head_cols", C.c_int32), ("cache_mb", C.c_int32)]
 
 
 class svm_result_t(C.Structure):
@@ -49,7 +51,9 @@ class svm_result_t(C.Structure):
                 ("n_launches", C.c_int32), ("grid_blocks", C.c_int32), ("ms_total", C.c_double),
                 ("ms_step", C.c_double), ("ms_recon", C.c_double), ("rows_streamed", C.c_int64),
                 ("nnz_streamed", C.c_int64), ("pattern_only", C.c_int32), ("lanes_per_row", C.c_int32),
-                ("ksum_mfma", C.c_int32), ("ms_ksum", C.c_double), ("recon_pairs", C.c_int64)]
+                ("ksum_mfma", C.c_int32), ("ms_ksum", C.c_double), ("recon_pairs", C.c_int64),
+                ("head_cols", C.c_int32), ("cache_rows", C.c_int32), ("rows_read", C.c_int64),
+                ("cache_values", C.c_int64), ("cache_both", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -70,8 +74,14 @@ def lib():
         L.svm_train_workspace_size.restype = C.c_size_t
         L.svm_train.argtypes = [P(svm_problem_t), P(svm_params_t), C.c_void_p, C.c_void_p, P(svm_result_t),
                                 C.c_void_p, C.c_size_t, C.c_void_p]
+        L.svm_train_shared_workspace_size.argtypes = [P(svm_problem_t), C.c_int32, P(C.c_void_p), P(svm_params_t)]
+        L.svm_train_shared_workspace_size.restype = C.c_size_t
+        L.svm_train_shared.argtypes = [P(svm_problem_t), C.c_int32, P(C.c_void_p), P(svm_params_t), P(C.c_void_p),
+                                       P(C.c_void_p), P(svm_result_t), C.c_void_p, C.c_size_t, C.c_void_p]
+        L.svm_decision_workspace_size.argtypes = [P(svm_problem_t), P(svm_problem_t), C.c_int32]
+        L.svm_decision_workspace_size.restype = C.c_size_t
         L.svm_decision.argtypes = [P(svm_problem_t), C.c_void_p, C.c_double, C.c_double, P(svm_problem_t),
-                                   C.c_void_p, C.c_int32, C.c_void_p]
+                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
         L.svm_train_batch.argtypes = [C.c_int32, P(svm_problem_t), P(svm_params_t), P(C.c_void_p), P(C.c_void_p),
                                       P(svm_result_t), C.c_void_p]
         L.svm_server_create.argtypes = [C.c_size_t, C.c_int32, P(C.c_void_p)]
@@ -141,9 +151,11 @@ def to_device(data, device="cuda", layout: Optional[int] = None, with_labels: bo
 
 
 def make_params(C_, gamma, eps=1e-3, shrink_mode=0, shrink_kind=0, shrink_param=0.0, max_iter=10**9,
-                kernel_precision=SVM_KERNEL_FP32, flags=0, grid_blocks=0, lanes_per_row=0) -> svm_params_t:
+                kernel_precision=SVM_KERNEL_FP32, flags=0, grid_blocks=0, lanes_per_row=0,
+                head_cols=0, cache_mb=0) -> svm_params_t:
     return svm_params_t(float(C_), float(gamma), float(eps), int(shrink_mode), int(shrink_kind), float(shrink_param),
-                        int(max_iter), int(kernel_precision), int(flags), int(grid_blocks), int(lanes_per_row))
+                        int(max_iter), int(kernel_precision), int(flags), int(grid_blocks), int(lanes_per_row),
+                        int(head_cols), int(cache_mb))
 
 
 def params_for(cfg, **kw) -> svm_params_t:
@@ -173,10 +185,41 @@ def svm_train(prob: DeviceProblem, params: svm_params_t, alpha, f=None, workspac
     return rc, res
 
 
+def svm_train_shared(prob: DeviceProblem, ys, params, alphas, fs=None, workspace=None, stream=None):
+    """Several problems over the samples of `prob` (its labels unused): ys[p] int8 device
+    labels, params[p] svm_params_t, alphas[p] / fs[p] float64 device tensors.  Returns (rc,
+    [svm_result_t])."""
+    k = len(ys)
+    yarr = (C.c_void_p * k)(*[t.data_ptr() for t in ys])
+    qarr = (svm_params_t * k)(*params)
+    aarr = (C.c_void_p * k)(*[a.data_ptr() for a in alphas])
+    farr = (C.c_void_p * k)(*[(f.data_ptr() if f is not None else None) for f in (fs or [None] * k)])
+    res = (svm_result_t * k)()
+    ws_ptr, ws_bytes = (None, 0) if workspace is None else (workspace.data_ptr(), workspace.numel())
+    rc = lib().svm_train_shared(C.byref(prob.s), k, yarr, qarr, aarr, farr, res, ws_ptr, ws_bytes,
+                                stream if stream is not None else current_stream_ptr())
+    return rc, [res[i] for i in range(k)]
+
+
+def svm_train_shared_workspace_size(prob: DeviceProblem, ys, params) -> int:
+    k = len(ys)
+    yarr = (C.c_void_p * k)(*[t.data_ptr() for t in ys])
+    qarr = (svm_params_t * k)(*params)
+    return int(lib().svm_train_shared_workspace_size(C.byref(prob.s), k, yarr, qarr))
+
+
+def svm_decision_workspace_size(train: DeviceProblem, queries: DeviceProblem,
+                                kernel_precision=SVM_KERNEL_FP32) -> int:
+    return int(lib().svm_decision_workspace_size(C.byref(train.s), C.byref(queries.s), int(kernel_precision)))
+
+
 def svm_decision(train: DeviceProblem, alpha, beta: float, gamma: float, queries: DeviceProblem, out,
-                 kernel_precision=SVM_KERNEL_FP32, stream=None) -> int:
+                 kernel_precision=SVM_KERNEL_FP32, workspace=None, stream=None) -> int:
+    """workspace: uint8 device tensor of at least svm_decision_workspace_size() bytes, or None
+    (the library then allocates its scratch on the stream)."""
+    ws_ptr, ws_bytes = (None, 0) if workspace is None else (workspace.data_ptr(), workspace.numel())
     return lib().svm_decision(C.byref(train.s), alpha.data_ptr(), float(beta), float(gamma), C.byref(queries.s),
-                              out.data_ptr(), int(kernel_precision),
+                              out.data_ptr(), int(kernel_precision), ws_ptr, ws_bytes,
                               stream if stream is not None else current_stream_ptr())
 
 

@@ -1,5 +1,8 @@
-"""Parity at the benchmark's full problem sizes, in the launch configuration bench.py times
-(automatic grid, lanes per row and residency; FP32 kernel values, FP64 f).
+"""Sampled checks at the full problem sizes of the three workloads (sparse binary n = 50,000,
+text-like n = 200,000 -- the benchmark's default --, dense mixture n = 500,000), in the launch
+configuration bench.py times (automatic grid, lanes per row, residency and head width; FP32
+kernel values, FP64 f).  The trained model itself is compared with the oracle's at the sizes
+the oracle can train (test_gpu_contract.py); here the checks hold at any size.
 
 The oracle cannot solve these sizes in test time, so the checks are the ones that hold at
 any size, with the oracle computing sampled outputs one by one from the GPU's alpha:
@@ -27,7 +30,7 @@ def S():
     return svmhip
 
 
-@pytest.mark.parametrize("which", [2, 4])
+@pytest.mark.parametrize("which", [2, 3, 4])
 def test_full_size_solution_against_sampled_oracle(S, which):
     cfg = g.CONFIGS[which]()
     data = cfg.data
