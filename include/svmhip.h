@@ -241,6 +241,28 @@ int svm_server_destroy(void* server);
 const char* svm_strerror(int code);
 int svm_version(void);
 
+/* ---- shape autotuner */
+#define SVM_TUNE_GRID 0           /* workgroups of svm_train's SMO loop */
+#define SVM_TUNE_TEAM 1           /* team size of a problem in svm_train_batch / the server */
+typedef struct {
+    int32_t target;               /* SVM_TUNE_GRID or SVM_TUNE_TEAM */
+    int32_t chosen;               /* the shape now used for problems of this class */
+    int32_t n_candidates;
+    int32_t reserved;
+    int32_t shape[8];             /* the candidates as launched */
+    double us_per_iter[8];        /* measured device time per SMO iteration of each */
+} svm_tune_t;
+/* Times a few launch shapes on `prob` (trial solves of its first iterations, on the device)
+ * and keeps the fastest for every later problem of its class when params.grid_blocks is 0: a
+ * class is the row layout, kernel precision, whether all CSR values are 1.0, whether
+ * shrinking is on, and n and d rounded up to powers of two.  The shapes only spread the work
+ * differently (the selection of eq:bminmax is exact and f is updated row by row), so results
+ * do not depend on them.  Allocates trial buffers; alpha of the problem is not touched.
+ * svm_autotune_reset forgets every class (the built-in rules apply again). */
+int svm_autotune(const svm_problem_t* prob, const svm_params_t* params, int32_t target, svm_tune_t* out,
+                 void* stream);
+int svm_autotune_reset(void);
+
 /* ---- test hooks */
 /* Two-threshold selection (eq:bminmax) over the samples listed in `active`
  * (n_active ids; order irrelevant), from f, alpha and y (device arrays of the

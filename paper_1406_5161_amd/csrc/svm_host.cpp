@@ -44,7 +44,7 @@ TraceCfg& trace_cfg() {
     return t;
 }
 int* last_step_info() {
-    static thread_local int v[3] = {0, 0, 0};
+    static thread_local int v[5] = {0, 0, 0, 0, 0};   // mode, grid, lanes per row, layout, values all 1.0
     return v;
 }
 unsigned long long*& prof_cfg() {
@@ -644,6 +644,9 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
     // 18.78 / 18.27 / 18.38 us at G = 192 / 224 / 256.
     const int cus = std::max(1, device_cu_count());
     int G = q->grid_blocks;
+    const TuneClass tclass{TUNE_GRID, S.lay, q->kernel_precision, S.pattern_only, q->shrink_mode != SVM_SHRINK_NONE,
+                           p->n, p->d};
+    if (!G) G = tuned_shape(tclass);   // measured by svm_autotune for this class
     if (!G) G = p->n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 224), (p->n + 350) / 700));
     G = std::min(G, p->n);
     const double avg_nnz = p->layout == SVM_CSR ? (double)hrp[p->n] / (double)p->n : 0.0;
@@ -685,6 +688,8 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
     last_step_info()[0] = plan.mode;
     last_step_info()[1] = G;
     last_step_info()[2] = S.lpr;
+    last_step_info()[3] = S.lay;
+    last_step_info()[4] = S.pattern_only ? 1 : 0;
     S.nseg_max = (p->n + G - 1) / G;
     S.nnz_seg_max = 0;
     if (!hrp.empty())
@@ -1273,6 +1278,104 @@ int svm_decision(const svm_problem_t* train, const double* alpha, double beta, d
     (void)hipFreeAsync(buf, s);
     (void)hipStreamSynchronize(s);
     return rc;
+}
+
+int svm_autotune(const svm_problem_t* prob, const svm_params_t* params, int32_t target, svm_tune_t* out,
+                 void* stream) {
+    int rc = check_problem(prob, true);
+    if (rc) return rc;
+    if ((rc = check_params(params))) return rc;
+    if ((target != SVM_TUNE_GRID && target != SVM_TUNE_TEAM) || (params->flags & SVM_FLAG_WARM_START))
+        return SVM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = prob->n;
+    // trial solves: the problem's first iterations, no closing recompute
+    svm_params_t q = *params;
+    q.max_iter = std::min<int64_t>(params->max_iter, 300);
+    q.flags |= SVM_FLAG_NO_FINAL_RECOMPUTE;
+    q.cache_mb = 0;
+    double* alpha = nullptr;
+    double* f = nullptr;
+    void* ws = nullptr;
+    if (hipMalloc((void**)&alpha, sizeof(double) * n) != hipSuccess) return SVM_ENOMEM;
+    if (hipMalloc((void**)&f, sizeof(double) * n) != hipSuccess) { (void)hipFree(alpha); return SVM_ENOMEM; }
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        if (ws) (void)hipFree(ws);
+        (void)hipFree(f);
+        (void)hipFree(alpha);
+    };
+    std::vector<int> cand;
+    auto add = [&](int v) {
+        v = std::max(1, v);
+        if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+    };
+    svm_result_t r{};
+    int lay = 0, pattern = 0;
+    if (target == SVM_TUNE_GRID) {
+        const int cus = std::max(1, device_cu_count());
+        const int g0 = n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 224), (n + 350) / 700));
+        for (int v : {g0 / 2, (3 * g0) / 4, g0, std::min(cus, (5 * g0) / 4), std::min(cus, (3 * g0) / 2)})
+            if (v <= n) add(v);
+        q.grid_blocks = cand.back();
+        const size_t bytes = svm_train_workspace_size(prob, &q);
+        if (!bytes || hipMalloc(&ws, bytes) != hipSuccess) { cleanup(); return SVM_ENOMEM; }
+    } else {
+        // the team rule needs the nonzero count and whether every value is 1.0: one trial
+        // solve on the automatic team tells the layout
+        q.grid_blocks = 0;
+        rc = svm_train_batch(1, prob, &q, &alpha, &f, &r, stream);
+        if (rc < 0) { cleanup(); return rc; }
+        const int64_t nnz = csr_nnz(prob, s);
+        bool pat = false;
+        if (prob->layout == SVM_CSR && (rc = csr_pattern_only(prob, reinterpret_cast<int32_t*>(f), s, &pat))) {
+            cleanup();
+            return rc;
+        }
+        const int t0 = batch_team_rule(prob, (int)std::max<int64_t>(nnz, 0), pat);
+        for (int v : {t0 / 2, t0, 2 * t0})
+            if (v <= TEAM_MAX) add(v);
+        lay = batch_layout(prob, pat);
+        pattern = pat ? 1 : 0;
+    }
+    if (out) {
+        memset(out, 0, sizeof(*out));
+        out->target = target;
+    }
+    double best = 0.0;
+    int chosen = 0;
+    const int nc = std::min<int>((int)cand.size(), 8);
+    for (int c = 0; c < nc; ++c) {
+        q.grid_blocks = cand[c];
+        double us = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {   // the second run is timed
+            if (target == SVM_TUNE_GRID) rc = train_impl(prob, &q, alpha, f, &r, ws, svm_train_workspace_size(prob, &q), s);
+            else rc = svm_train_batch(1, prob, &q, &alpha, &f, &r, stream);
+            if (rc < 0) { cleanup(); return rc; }
+            us = r.iterations > 0 ? r.ms_step * 1e3 / (double)r.iterations : 0.0;
+        }
+        const int used = r.grid_blocks;
+        if (target == SVM_TUNE_GRID) {
+            lay = last_step_info()[3];
+            pattern = last_step_info()[4];
+        }
+        if (out) { out->shape[c] = used; out->us_per_iter[c] = us; }
+        if (!chosen || us < best) { best = us; chosen = used; }
+    }
+    cleanup();
+    const TuneClass tc{target == SVM_TUNE_GRID ? TUNE_GRID : TUNE_TEAM, lay, params->kernel_precision, pattern != 0,
+                       params->shrink_mode != SVM_SHRINK_NONE, n, prob->d};
+    set_tuned_shape(tc, chosen);
+    if (out) {
+        out->n_candidates = nc;
+        out->chosen = chosen;
+    }
+    return SVM_OK;
+}
+
+int svm_autotune_reset(void) {
+    clear_tuned_shapes();
+    return SVM_OK;
 }
 
 int svm_debug_select(int32_t n_active, const int32_t* active, const double* f, const double* alpha, const int8_t* y,

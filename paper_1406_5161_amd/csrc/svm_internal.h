@@ -267,6 +267,21 @@ hipError_t launch_shared(const SharedArgs& a, int G, int kprec, hipStream_t s);
 int shared_max_blocks(int lay, int kprec, size_t lds);
 size_t shared_lds_bytes(int lay, int d);
 
+// ---- shape autotuner (svm_tune.cpp): measured shapes per problem class, per process
+enum : int { TUNE_GRID = 0, TUNE_TEAM = 1 };
+struct TuneClass {
+    int target;               // TUNE_GRID (svm_train workgroups) or TUNE_TEAM (batched team size)
+    int lay, kprec;
+    bool pattern, shrink;
+    long long n, d;
+};
+int tuned_shape(const TuneClass& c);   // 0: not tuned
+void set_tuned_shape(const TuneClass& c, int shape);
+void clear_tuned_shapes();
+// the batched solver's team-size rule for a problem (svm_serve.cpp), and its layout there
+int batch_team_rule(const svm_problem_t* p, int nnz, bool pattern);
+int batch_layout(const svm_problem_t* p, bool pattern);
+
 // svm_decision on a caller-given device workspace (svm_host.cpp); *need receives the bytes the
 // problem needs (SVM_EWORKSPACE when ws_bytes is smaller).
 int decision_in_workspace(const svm_problem_t* train, const double* alpha, double beta, double gamma,

@@ -126,9 +126,12 @@ struct Inspect {
 // loop never reads rows from HBM, when a member then holds at least 512 rows and the team
 // needs at most TEAM_MAX workgroups; else about 1500 rows per workgroup (at most TEAM_MAX)
 // streamed from HBM.  Never more than the launch's workgroups.
-int team_size(const svm_problem_t* p, const Inspect& in, int workers, int requested) {
+int team_size(const svm_problem_t* p, const Inspect& in, int workers, int requested, int kprec, bool shrink) {
     const int cap = std::max(1, std::min(TEAM_MAX, workers));
     if (requested > 0) return std::min(requested, cap);
+    // a team size measured by svm_autotune for this problem's class comes first
+    const TuneClass c{TUNE_TEAM, batch_layout(p, in.pattern != 0), kprec, in.pattern != 0, shrink, p->n, p->d};
+    if (const int t = tuned_shape(c)) return std::min(t, cap);
     const bool dense = p->layout != SVM_CSR;
     const bool bits = bits_capable(p) && in.pattern;
     const int W = dense ? dpad4(p->d) : bits ? bits_wpr(p->d) : p->d;
@@ -472,7 +475,8 @@ struct Server {
             }
             j.in.nnz = o.nnz;
             j.in.pattern = o.pattern;
-            j.team = team_size(&j.w.prob, j.in, workgroups, j.w.params.grid_blocks);
+            j.team = team_size(&j.w.prob, j.in, workgroups, j.w.params.grid_blocks, j.w.params.kernel_precision,
+                               j.w.params.shrink_mode != SVM_SHRINK_NONE);
             while (j.team > 1 && j.base_bytes + prob_bytes(&j.w.prob, true, j.team, TEAM_MAX).team > budget) j.team /= 2;
             j.team_bytes = prob_bytes(&j.w.prob, true, j.team, TEAM_MAX).team;
             const double row = j.w.prob.layout == SVM_CSR ? (bits_capable(&j.w.prob) && j.in.pattern
@@ -569,6 +573,17 @@ struct Server {
 
 }  // namespace
 
+int svm::batch_team_rule(const svm_problem_t* p, int nnz, bool pattern) {
+    Inspect in;
+    in.nnz = nnz;
+    in.pattern = pattern ? 1 : 0;
+    return team_size(p, in, std::max(1, batch_max_workgroups(SVM_KERNEL_FP32)), 0, -1, false);
+}
+
+int svm::batch_layout(const svm_problem_t* p, bool pattern) {
+    return p->layout != SVM_CSR ? LAY_DENSE : (bits_capable(p) && pattern) ? LAY_BITS : LAY_CSR_TABLE;
+}
+
 extern "C" {
 
 int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* params, double* const* alpha,
@@ -595,7 +610,8 @@ int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* p
             (void)hipFree(ictl);
             return rc;
         }
-        team[p] = team_size(&probs[p], ins[p], wg, params[p].grid_blocks);
+        team[p] = team_size(&probs[p], ins[p], wg, params[p].grid_blocks, params[p].kernel_precision,
+                            params[p].shrink_mode != SVM_SHRINK_NONE);
         nt += team[p];
     }
     (void)hipFree(ictl);

@@ -28,10 +28,29 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v), q))
 
 
+def tune_classes(S, cfgs, probs, params, log=print) -> dict:
+    """Team sizes of the batched solver measured by svm_autotune on the first problem of every
+    class in the stream (row kind and n rounded up to a power of two), before the clock starts;
+    the server then uses them for every problem of the class."""
+    import math
+    seen = {}
+    for c, dp, p in zip(cfgs, probs, params):
+        key = "%s_n2^%d" % (c.data.name.split("_", 1)[1], math.ceil(math.log2(c.data.n)))
+        if key in seen:
+            continue
+        rc, info = S.svm_autotune(dp, p, S.SVM_TUNE_TEAM)
+        assert rc == S.SVM_OK, S.strerror(rc)
+        seen[key] = {"chosen": info["chosen"],
+                     "us_per_iter": {str(x["shape"]): round(x["us_per_iter"], 2) for x in info["candidates"]}}
+    log("serving: tuned team sizes of %d classes" % len(seen))
+    return dict(sorted(seen.items()))
+
+
 def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budget_gb: float = 64.0,
-        workers: int = 16, detail: list | None = None, plain: bool = True) -> dict:
+        workers: int = 16, detail: list | None = None, plain: bool = True, tune: bool = True) -> dict:
     """Runs both paths on the same trace; with `detail` (a list) appends one record per problem:
-    shape, team size, iterations and device / host times of both paths."""
+    shape, team size, iterations and device / host times of both paths.  With `tune`, the
+    batched path's team sizes come from svm_autotune per class (measured before the clock)."""
     import torch
     from . import svmhip as S
     t_gen = time.perf_counter()
@@ -41,6 +60,8 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
     probs = [S.to_device(c.data) for c in cfgs]
     params = [S.params_for(c) for c in cfgs]
     torch.cuda.synchronize()
+    S.svm_autotune_reset()
+    tuned = tune_classes(S, cfgs, probs, params, log) if tune else None
 
     # ---- plain loop: one problem at a time, FIFO, each waits for its arrival; one workspace of
     # the largest size serves every solve, so no solve allocates inside the timed loop
@@ -118,6 +139,7 @@ def run(num: int = 256, rate_hz: float = 200.0, log=print, slots: int = 0, budge
         "dual_rel_diff_max": max(rel), "dual_rel_diff_median": float(np.median(rel)),
         "dual_rel_diff_over_1e-6": int(sum(1 for v in rel if v > 1e-6)) if plain else None,
         "plain_workspace": "one preallocated workspace of the largest size",
+        "tuned_team_sizes": tuned,
     }
     log("serving: plain %.2f solves/s (p99 %.2f s), batched %.2f solves/s (p99 %.2f s), speedup %.2fx"
         % (out["plain"]["solves_per_s"], out["plain"]["p99_latency_s"], out["batched"]["solves_per_s"],

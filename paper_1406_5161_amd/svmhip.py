@@ -25,7 +25,7 @@ SVM_FLAG_NO_LDS_PAYLOAD, SVM_FLAG_NO_LDS_STATE, SVM_FLAG_NO_BITSETS = 4, 8, 16
 
 EXPORTS = ["svm_train_workspace_size", "svm_train", "svm_train_shared_workspace_size", "svm_train_shared",
            "svm_decision_workspace_size", "svm_decision",
-           "svm_train_batch", "svm_server_create",
+           "svm_train_batch", "svm_autotune", "svm_autotune_reset", "svm_server_create",
            "svm_server_submit", "svm_server_poll", "svm_server_drain", "svm_server_stats", "svm_server_destroy",
            "svm_strerror", "svm_version", "svm_debug_select", "svm_debug_set_trace", "svm_debug_set_profile",
            "svm_debug_step_info"]
@@ -42,6 +42,19 @@ class svm_params_t(C.Structure):
                 ("shrink_kind", C.c_int32), ("shrink_param", C.c_double), ("max_iter", C.c_int64),
                 ("kernel_precision", C.c_int32), ("flags", C.c_uint32), ("grid_blocks", C.c_int32),
                 ("lanes_per_row", C.c_int32), ("head_cols", C.c_int32), ("cache_mb", C.c_int32)]
+
+
+SVM_TUNE_GRID, SVM_TUNE_TEAM = 0, 1
+
+
+class svm_tune_t(C.Structure):
+    _fields_ = [("target", C.c_int32), ("chosen", C.c_int32), ("n_candidates", C.c_int32), ("reserved", C.c_int32),
+                ("shape", C.c_int32 * 8), ("us_per_iter", C.c_double * 8)]
+
+    def as_dict(self):
+        k = self.n_candidates
+        return {"target": self.target, "chosen": self.chosen,
+                "candidates": [{"shape": self.shape[i], "us_per_iter": self.us_per_iter[i]} for i in range(k)]}
 
 
 class svm_result_t(C.Structure):
@@ -82,6 +95,7 @@ def lib():
         L.svm_decision_workspace_size.restype = C.c_size_t
         L.svm_decision.argtypes = [P(svm_problem_t), C.c_void_p, C.c_double, C.c_double, P(svm_problem_t),
                                    C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.svm_autotune.argtypes = [P(svm_problem_t), P(svm_params_t), C.c_int32, P(svm_tune_t), C.c_void_p]
         L.svm_train_batch.argtypes = [C.c_int32, P(svm_problem_t), P(svm_params_t), P(C.c_void_p), P(C.c_void_p),
                                       P(svm_result_t), C.c_void_p]
         L.svm_server_create.argtypes = [C.c_size_t, C.c_int32, P(C.c_void_p)]
@@ -221,6 +235,18 @@ def svm_decision(train: DeviceProblem, alpha, beta: float, gamma: float, queries
     return lib().svm_decision(C.byref(train.s), alpha.data_ptr(), float(beta), float(gamma), C.byref(queries.s),
                               out.data_ptr(), int(kernel_precision), ws_ptr, ws_bytes,
                               stream if stream is not None else current_stream_ptr())
+
+
+def svm_autotune(prob: DeviceProblem, params: svm_params_t, target: int, stream=None):
+    """Returns (rc, dict of the candidates timed and the shape chosen)."""
+    t = svm_tune_t()
+    rc = lib().svm_autotune(C.byref(prob.s), C.byref(params), int(target), C.byref(t),
+                            stream if stream is not None else current_stream_ptr())
+    return rc, t.as_dict()
+
+
+def svm_autotune_reset() -> int:
+    return lib().svm_autotune_reset()
 
 
 def svm_debug_select(active, f, alpha, y, C_, num_blocks=0, stream=None):
