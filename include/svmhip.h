@@ -51,6 +51,7 @@ extern "C" {
 #define SVM_ENOMEM (-7)          /* an internal allocation failed (server budget exhausted, ...) */
 #define SVM_EBUSY (-8)           /* serving: the ticket is still running */
 #define SVM_EABORT (-9)          /* the device loop stopped on its watchdog (barrier wait timed out) */
+#define SVM_ESCRATCH (-10)       /* svm_decision_noalloc: the problem needs more than its built-in scratch */
 
 /* ---- sample layouts */
 #define SVM_DENSE_ROW_MAJOR 0     /* x[i*ldx + k], ldx >= d */
@@ -190,6 +191,17 @@ size_t svm_decision_workspace_size(const svm_problem_t* train, const svm_problem
 int svm_decision(const svm_problem_t* train, const double* alpha, double beta, double gamma,
                  const svm_problem_t* queries, double* out, int32_t kernel_precision, void* workspace,
                  size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): svm_decision with the same arguments minus the workspace, running on a 96 MiB
+ * scratch array that the library keeps in each GPU's memory from the first call on that GPU
+ * until the process ends.  It calls no allocator.  Like svm_decision it reads its validation
+ * results back and synchronises `stream`, so it cannot be recorded into a HIP graph.  A problem
+ * whose scratch (svm_decision_workspace_size) exceeds 96 MiB returns SVM_ESCRATCH.  Every call
+ * on one GPU uses that GPU's array: calls that overlap in time on one GPU (from several host
+ * threads, or on streams that run concurrently) race and their outputs are undefined. */
+int svm_decision_noalloc(const svm_problem_t* train, const double* alpha, double beta, double gamma,
+                         const svm_problem_t* queries, double* out, int32_t kernel_precision, void* stream);
 
 /* Several independent problems in one persistent fused launch: problem p is
  * solved by its own team of workgroups (one to 64: the smallest team whose

@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsvmhip.so")
-SOURCES = ["svm_step.hip", "svm_batch.hip", "svm_kernels.hip", "svm_ksum_ht.hip", "svm_shared.hip", "svm_host.cpp", "svm_serve.cpp", "svm_tune.cpp"]
+SOURCES = ["svm_step.hip", "svm_batch.hip", "svm_kernels.hip", "svm_ksum_ht.hip", "svm_shared.hip", "svm_noalloc.hip", "svm_host.cpp", "svm_serve.cpp", "svm_tune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

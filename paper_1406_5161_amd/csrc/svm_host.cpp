@@ -1440,6 +1440,7 @@ const char* svm_strerror(int code) {
         case SVM_ENOMEM: return "device allocation failed or memory budget exhausted";
         case SVM_EBUSY: return "ticket still queued or running";
         case SVM_EABORT: return "device loop stopped by its barrier watchdog";
+        case SVM_ESCRATCH: return "the problem needs more scratch than the 96 MiB built-in array of svm_decision_noalloc";
         default: return "unknown status code";
     }
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libsvmhip.so")
 
 SVM_OK, SVM_NOT_CONVERGED = 0, 1
 SVM_EINVAL, SVM_EONECLASS, SVM_ENONFINITE, SVM_EWORKSPACE, SVM_EHIP = -1, -2, -3, -4, -5
-SVM_EUNSUPPORTED, SVM_ENOMEM, SVM_EBUSY, SVM_EABORT = -6, -7, -8, -9
+SVM_EUNSUPPORTED, SVM_ENOMEM, SVM_EBUSY, SVM_EABORT, SVM_ESCRATCH = -6, -7, -8, -9, -10
 SVM_DENSE_ROW_MAJOR, SVM_DENSE_FEATURE_MAJOR, SVM_CSR = 0, 1, 2
 SVM_KERNEL_FP32, SVM_KERNEL_FP64 = 0, 1
 SVM_FLAG_WARM_START, SVM_FLAG_NO_FINAL_RECOMPUTE = 1, 2
@@ -25,7 +25,7 @@ SVM_FLAG_NO_LDS_PAYLOAD, SVM_FLAG_NO_LDS_STATE, SVM_FLAG_NO_BITSETS = 4, 8, 16
 
 EXPORTS = ["svm_train_workspace_size", "svm_train", "svm_train_shared_workspace_size", "svm_train_shared",
            "svm_decision_workspace_size", "svm_decision",
-           "svm_train_batch", "svm_autotune", "svm_autotune_reset", "svm_server_create",
+           "svm_decision_noalloc", "svm_train_batch", "svm_autotune", "svm_autotune_reset", "svm_server_create",
            "svm_server_submit", "svm_server_poll", "svm_server_drain", "svm_server_stats", "svm_server_destroy",
            "svm_strerror", "svm_version", "svm_debug_select", "svm_debug_set_trace", "svm_debug_set_profile",
            "svm_debug_step_info"]
@@ -95,6 +95,8 @@ def lib():
         L.svm_decision_workspace_size.restype = C.c_size_t
         L.svm_decision.argtypes = [P(svm_problem_t), C.c_void_p, C.c_double, C.c_double, P(svm_problem_t),
                                    C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.svm_decision_noalloc.argtypes = [P(svm_problem_t), C.c_void_p, C.c_double, C.c_double, P(svm_problem_t),
+                                           C.c_void_p, C.c_int32, C.c_void_p]
         L.svm_autotune.argtypes = [P(svm_problem_t), P(svm_params_t), C.c_int32, P(svm_tune_t), C.c_void_p]
         L.svm_train_batch.argtypes = [C.c_int32, P(svm_problem_t), P(svm_params_t), P(C.c_void_p), P(C.c_void_p),
                                       P(svm_result_t), C.c_void_p]
@@ -235,6 +237,14 @@ def svm_decision(train: DeviceProblem, alpha, beta: float, gamma: float, queries
     return lib().svm_decision(C.byref(train.s), alpha.data_ptr(), float(beta), float(gamma), C.byref(queries.s),
                               out.data_ptr(), int(kernel_precision), ws_ptr, ws_bytes,
                               stream if stream is not None else current_stream_ptr())
+
+
+def svm_decision_noalloc(train: DeviceProblem, alpha, beta: float, gamma: float, queries: DeviceProblem, out,
+                         kernel_precision=SVM_KERNEL_FP32, stream=None) -> int:
+    """svm_decision on the library's built-in scratch (no allocation)."""
+    return lib().svm_decision_noalloc(C.byref(train.s), alpha.data_ptr(), float(beta), float(gamma),
+                                      C.byref(queries.s), out.data_ptr(), int(kernel_precision),
+                                      stream if stream is not None else current_stream_ptr())
 
 
 def svm_autotune(prob: DeviceProblem, params: svm_params_t, target: int, stream=None):
