@@ -265,7 +265,11 @@ typedef struct {
     double us_per_iter[8];        /* measured device time per SMO iteration of each */
 } svm_tune_t;
 /* Times a few launch shapes on `prob` (trial solves of its first iterations, on the device)
- * and keeps the fastest for every later problem of its class when params.grid_blocks is 0: a
+ * and keeps one for every later problem of its class when params.grid_blocks is 0 -- for
+ * SVM_TUNE_GRID the fastest (the problem has the GPU to itself), for SVM_TUNE_TEAM the one with
+ * the fewest workgroup-microseconds per iteration among those within 1.5x of the fastest time
+ * per iteration (a team shares the launch with other problems, so its cost is workgroups held
+ * times time, with a bound on how much slower one problem may get): a
  * class is the row layout, kernel precision, whether all CSR values are 1.0, whether
  * shrinking is on, and n and d rounded up to powers of two.  The shapes only spread the work
  * differently (the selection of eq:bminmax is exact and f is updated row by row), so results

@@ -1,14 +1,16 @@
 // svm_batch.hip -- many independent training problems in one persistent launch.
 //
-// One workgroup solves one whole problem: the SMO loop of Alg. 2 / Alg. 4, the
-// shrinking driver of Alg. 5 (or its multi-reconstruction variant), gradient
-// reconstruction (Alg. 6), the closing FP64-accumulated recompute of f and the
-// threshold of the paper's Sec. 3.1 all run inside the workgroup, so problems
-// never wait for each other and a problem's result does not depend on what
-// else is resident.  Workgroups take problems by ticket from a descriptor
-// ring; when serving, the host keeps publishing descriptors into pinned
-// memory while the loop runs (continuous batching) and the loop ends once the
-// host asks it to and the ring is drained.
+// Each problem is solved by its own team of 1 to 64 workgroups, each member owning a
+// contiguous segment of the samples: the SMO loop of Alg. 2 / Alg. 4, the shrinking
+// driver of Alg. 5 (or its multi-reconstruction variant), gradient reconstruction
+// (Alg. 6), the closing FP64-accumulated recompute of f and the threshold of the
+// paper's Sec. 3.1 all run inside the team, whose members meet only in tag-validated
+// record exchanges with an exact merge, so problems never wait for each other and a
+// problem's result depends neither on its team size nor on what else is resident.
+// Workgroups take worker tickets (problem, rank in its team) in order; when serving,
+// the host keeps publishing descriptors and tickets into pinned memory while the loop
+// runs (continuous batching) and the loop ends once the host asks it to and the rings
+// are drained.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>

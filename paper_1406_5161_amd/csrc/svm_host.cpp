@@ -60,7 +60,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 struct Plan {
     size_t ctl, xpack, bits, fint, status, mask, act, seg, cnt, rec, listw, listz, coef, blkcnt, counts, part,
         sumblk, out6, work, htcnt, hthmap, htbits, hthead, htnrm, httcnt, htmisc, htbhead, htbnrm, httoff, httent,
-        kcache, ktags, total;
+        kcache, ktags, col16, val2, total;
     int64_t cache_rows;   // slots of the kernel-row cache (0: none)
     int tag_grid;         // workgroups the cache tags are sized for
 };
@@ -150,6 +150,10 @@ Plan make_plan(const svm_problem_t* p, const svm_params_t* params, int64_t nnz) 
     const size_t vb = params && params->kernel_precision == SVM_KERNEL_FP64 ? 8 : 4;
     q.kcache = take((size_t)q.cache_rows * n * vb);
     q.ktags = take(sizeof(unsigned long long) * (size_t)q.cache_rows * q.tag_grid);
+    // CSR rows as element pairs for the loop's HBM stream (u16 columns and a copy of the values)
+    const size_t npad = p->layout == SVM_CSR ? (size_t)std::max<int64_t>(nnz, 0) + 2 : 0;
+    q.col16 = take(sizeof(uint16_t) * npad);
+    q.val2 = take(sizeof(float) * npad);
     q.total = o;
     return q;
 }
@@ -297,6 +301,8 @@ struct Solver {
     double* out6;
     const float* xin;      // dense values the kernels read (packed)
     uint32_t* bits = nullptr;   // LAY_BITS rows
+    uint32_t* col2 = nullptr;   // CSR rows as element pairs (LAY_CSR_TABLE / LAY_CSR_SLOT)
+    float* val2 = nullptr;
     HtBufs ht{};                // wide CSR: dense head rows for the kernel sums
     int ht_H = 0;               // head columns in use (0: sparse kernel sums only)
     double t_start = 0;         // host clock at the start of the call
@@ -469,6 +475,7 @@ struct Solver {
         a.bits = bits;
         a.wpr = lay == LAY_BITS ? bits_wpr(d) : 0;
         a.row_ptr = p->row_ptr; a.col = p->col; a.val = p->val;
+        a.col2 = col2; a.val2 = val2;
         a.pattern_only = pattern_only ? 1 : 0;
         a.max_row_nnz = max_row_nnz;
         a.y = p->y;
@@ -593,6 +600,12 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
             S.lpr = 1;
             S.bits = S.at<uint32_t>(S.plan.bits);
             HIP_TRY(launch_pack_bits(p->n, p->d, bits_wpr(p->d), p->row_ptr, p->col, S.bits, s));
+        } else {
+            // rows the loop may stream from HBM: u16 column pairs and float2 value pairs
+            S.col2 = S.at<uint32_t>(S.plan.col16);
+            S.val2 = S.at<float>(S.plan.val2);
+            HIP_TRY(launch_pack_pairs(nnz, p->col, p->val, S.pattern_only ? 1 : 0,
+                                      reinterpret_cast<uint16_t*>(S.col2), S.val2, s));
         }
         if (S.lay == LAY_CSR_SLOT && ht_capable(p) && q->kernel_precision == SVM_KERNEL_FP32 && q->head_cols != -1) {
             // the most frequent columns as dense rows for the matrix cores in the kernel sums
@@ -1344,6 +1357,7 @@ int svm_autotune(const svm_problem_t* prob, const svm_params_t* params, int32_t 
     }
     double best = 0.0;
     int chosen = 0;
+    std::vector<std::pair<int, double>> shape_us;
     const int nc = std::min<int>((int)cand.size(), 8);
     for (int c = 0; c < nc; ++c) {
         q.grid_blocks = cand[c];
@@ -1360,9 +1374,20 @@ int svm_autotune(const svm_problem_t* prob, const svm_params_t* params, int32_t 
             pattern = last_step_info()[4];
         }
         if (out) { out->shape[c] = used; out->us_per_iter[c] = us; }
+        shape_us.push_back({used, us});
         if (!chosen || us < best) { best = us; chosen = used; }
     }
     cleanup();
+    if (target == SVM_TUNE_TEAM) {
+        // teams share the launch with other problems: the fewest workgroup-microseconds per
+        // iteration among the shapes within 1.5x of the fastest one's time per iteration
+        double cost = 0.0;
+        for (const auto& c : shape_us)
+            if (c.second <= 1.5 * best && (cost == 0.0 || c.first * c.second < cost)) {
+                cost = c.first * c.second;
+                chosen = c.first;
+            }
+    }
     const TuneClass tc{target == SVM_TUNE_GRID ? TUNE_GRID : TUNE_TEAM, lay, params->kernel_precision, pattern != 0,
                        params->shrink_mode != SVM_SHRINK_NONE, n, prob->d};
     set_tuned_shape(tc, chosen);

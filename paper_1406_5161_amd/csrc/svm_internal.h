@@ -109,6 +109,10 @@ struct StepArgs {
     unsigned long long* tags; // [G][cache_rows]
     int32_t cache_rows;
     uint32_t epoch;           // tag epoch of this launch (> 0; the host zeroes the tags per solve)
+    // CSR rows streamed from HBM: element pairs (2q, 2q+1) of the CSR arrays as one word of two
+    // u16 column ids and two floats (1.0 when all values are 1.0), padded with zeros past nnz
+    const uint32_t* col2;     // [(nnz + 2) / 2]
+    const float* val2;        // [(nnz + 2) / 2 * 2], 8-byte aligned
 };
 
 // Residency of a workgroup's segment during one launch of the SMO loop:
@@ -191,6 +195,10 @@ hipError_t launch_refresh_status(int n, const double* alpha, const int8_t* y, do
 hipError_t launch_summary(int n, const double* alpha, const double* f, const int8_t* y, double C, double* blk,
                           double* out6, hipStream_t s);
 hipError_t launch_check_pattern(int nnz, const float* val, int32_t* flag, hipStream_t s);
+// CSR columns as u16 and values (1.0 where pattern_only) copied into element pairs for the SMO
+// loop's HBM stream, with two zero elements past nnz (d <= 65,536)
+hipError_t launch_pack_pairs(int64_t nnz, const int32_t* col, const float* val, int pattern_only, uint16_t* col16,
+                             float* val2, hipStream_t s);
 
 int device_cu_count();
 

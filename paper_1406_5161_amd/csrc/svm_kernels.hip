@@ -842,4 +842,21 @@ hipError_t launch_check_pattern(int nnz, const float* val, int32_t* flag, hipStr
     return hipGetLastError();
 }
 
+__global__ void pack_pairs_kernel(int64_t nnz, const int32_t* __restrict__ col, const float* __restrict__ val,
+                                  int pattern_only, uint16_t* col16, float* val2) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz + 2; p += (int64_t)gridDim.x * blockDim.x) {
+        const bool in = p < nnz;
+        col16[p] = in ? (uint16_t)col[p] : (uint16_t)0;
+        val2[p] = in ? (pattern_only ? 1.f : val[p]) : 0.f;
+    }
+}
+
+hipError_t launch_pack_pairs(int64_t nnz, const int32_t* col, const float* val, int pattern_only, uint16_t* col16,
+                             float* val2, hipStream_t s) {
+    if (nnz < 0) return hipErrorInvalidValue;
+    const int64_t blocks = std::min<int64_t>((nnz + 2 + 255) / 256, 4096);
+    pack_pairs_kernel<<<(unsigned)blocks, 256, 0, s>>>(nnz, col, val, pattern_only, col16, val2);
+    return hipGetLastError();
+}
+
 }  // namespace svm

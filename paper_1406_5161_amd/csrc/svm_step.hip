@@ -493,25 +493,38 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                             sl2 += v * (KT)ul.y;
                         }
                     } else {
-                        // columns and values from HBM: CB of them are loaded before any is used
-                        constexpr int CB = 8;
-                        for (int pb = p0 + gl; pb < p1; pb += LPR * CB) {
-                            int cc[CB];
-                            float vf[CB];
+                        // columns and values from HBM as element pairs (2q, 2q+1): one word of
+                        // two u16 ids and one float2 per pair, CB2 pairs loaded before any is
+                        // used; elements of the first and last pair outside the row count zero
+                        constexpr int CB2 = 5;
+                        const int e0 = gbase + p0, e1 = gbase + p1;
+                        const int q1 = (e1 + 1) >> 1;
+                        const float2* v2 = reinterpret_cast<const float2*>(A.val2);
+                        for (int qb = (e0 >> 1) + gl; qb < q1; qb += LPR * CB2) {
+                            uint32_t cc[CB2];
+                            float2 vv[CB2];
 #pragma unroll
-                            for (int u = 0; u < CB; ++u) {
-                                const int p = pb + u * LPR;
-                                cc[u] = p < p1 ? A.col[gbase + p] : -1;
-                                vf[u] = (p < p1 && !A.pattern_only) ? A.val[gbase + p] : 1.f;
+                            for (int u = 0; u < CB2; ++u) {
+                                const int q = qb + u * LPR;
+                                cc[u] = q < q1 ? A.col2[q] : 0u;
+                                vv[u] = q < q1 ? v2[q] : make_float2(0.f, 0.f);
                             }
 #pragma unroll
-                            for (int u = 0; u < CB; ++u) {
-                                if (cc[u] < 0) break;
-                                const KT v = (KT)vf[u];
-                                const float2 ul = (LAY == LAY_CSR_TABLE) ? pairv[cc[u]] : pairv[slot[cc[u]]];
-                                nn += v * v;
-                                su += v * (KT)ul.x;
-                                sl2 += v * (KT)ul.y;
+                            for (int u = 0; u < CB2; ++u) {
+                                const int q = qb + u * LPR;
+                                if (q >= q1) break;
+                                const int e = 2 * q;
+                                const KT va = e >= e0 ? (KT)vv[u].x : (KT)0;
+                                const KT vb = e + 1 < e1 ? (KT)vv[u].y : (KT)0;
+                                const int ca = (int)(cc[u] & 0xffffu), cb = (int)(cc[u] >> 16);
+                                const float2 ua = (LAY == LAY_CSR_TABLE) ? pairv[ca] : pairv[slot[ca]];
+                                const float2 ub = (LAY == LAY_CSR_TABLE) ? pairv[cb] : pairv[slot[cb]];
+                                nn += va * va;
+                                su += va * (KT)ua.x;
+                                sl2 += va * (KT)ua.y;
+                                nn += vb * vb;
+                                su += vb * (KT)ub.x;
+                                sl2 += vb * (KT)ub.y;
                             }
                         }
                     }
