@@ -375,7 +375,6 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         // ---- 2. f update over the active rows of this segment, candidates, shrink rule
         double cbu = INFINITY, cbl = -INFINITY;
         int ciu = IDX_NONE, cil = IDX_NONE;
-        int newcount = 0;
         work_rows += (unsigned long long)nrows;
         if constexpr (CACHE) {
             if (need_row) work_payload += (unsigned long long)nrows;
@@ -409,22 +408,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
             }
             return keep;
         };
-        // stable in-place compaction of one chunk of the active list (every thread calls it)
-        auto compact = [&](bool keep, int li, int i) {
-            const unsigned long long m = __ballot(keep);
-            const int wpre = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) s_wc[wid] = __popcll(m);
-            __syncthreads();
-            int off = 0, tot = 0;
-            for (int w = 0; w < NW; ++w) {
-                int c = s_wc[w];
-                off += (w < wid) ? c : 0;
-                tot += c;
-            }
-            if (keep) L[newcount + off + wpre] = (MODE == STEP_GLOBAL) ? i : li;
-            newcount += tot;
-            __syncthreads();
-        };
+        // a row the shrink rule removes is marked in its own entry of the active list (-1); the
+        // list is compacted once at the end of the pass, so the stream has no barriers
         bool rows_done = false;
         if constexpr (CACHE) {
             if (!need_row) {
@@ -438,7 +423,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     const int i = seg0 + li;
                     bool keep = false;
                     if (valid) keep = update_row(li, i, (double)cu[i], (double)cl[i]);
-                    if (do_shrink) compact(keep, li, i);
+                    if (do_shrink && valid && !keep) L[t] = -1;
                 }
                 rows_done = true;
             }
@@ -556,9 +541,31 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     keep = update_row(li, i, ku, kl);
                 }
             }
-            if (do_shrink) compact(keep, li, i);
+            if (do_shrink && valid && gl == 0 && !keep) L[t] = -1;
         }
-        if (do_shrink) nrows = newcount;
+        if (do_shrink) {
+            // stable in-place compaction of the marked list: every chunk is read before its
+            // first barrier and written only below its own start
+            __syncthreads();
+            int newcount = 0;
+            for (int base = 0; base < nrows; base += BLOCK) {
+                const int t = base + tid;
+                const int v = t < nrows ? L[t] : -1;
+                const unsigned long long m = __ballot(v >= 0);
+                if (lane == 0) s_wc[wid] = __popcll(m);
+                __syncthreads();
+                int off = 0, tot = 0;
+                for (int w = 0; w < NW; ++w) {
+                    const int c = s_wc[w];
+                    off += (w < wid) ? c : 0;
+                    tot += c;
+                }
+                if (v >= 0) L[newcount + off + __popcll(m & ((1ull << lane) - 1ull))] = v;
+                newcount += tot;
+                __syncthreads();
+            }
+            nrows = newcount;
+        }
         if constexpr (CACHE) {
             if (tid == 0) {
                 unsigned long long* tg = A.tags + (size_t)A.cache_rows * blk;
