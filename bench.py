@@ -12,8 +12,11 @@ before the timed region starts.
 Prints ONE JSON line.  ``value`` is SMO iterations per second over the timed solves;
 ``train_s`` is seconds to KKT at eps = 1e-3.  ``roofline`` is the SMO loop kernel's
 algorithmic bytes (rows and nonzeros it actually streamed, times the per-row / per-nonzero
-byte counts below) over its HIP-event-timed duration; ``reconstruction`` gives the kernel
-sums' matrix-core rate.  ``serving`` is the batched / serving comparison on the 256-problem
+byte counts below, plus the kernel-row cache values it read or wrote) over its HIP-event-timed
+duration; the loop's CSR stream moves 6 of the 8 bytes per nonzero counted there (u16 column
+ids), which ``traffic`` (HBM counters) shows.  ``reconstruction`` gives the kernel sums'
+matrix-core rate.  The text-like workload runs with a 160 GiB kernel-row cache by default
+(``--cache-mb 0`` turns it off).  ``serving`` is the batched / serving comparison on the 256-problem
 Poisson stream (``--no-serve`` skips it).  ``cpu_baseline`` is the FP64 oracle on the host
 cores (all of them, and one) on a bounded sample of the same solve.
 """
@@ -32,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_COUNTERS = {
     "cfg2_sparse_binary_n50000_d300": os.path.join(ROOT, "profiles", "smo_loop_cfg2_traffic.json"),
     "cfg4_mixture_n500000_d28": os.path.join(ROOT, "profiles", "smo_loop_cfg4_traffic.json"),
+    "cfg3_text_n200000_d47000": os.path.join(ROOT, "profiles", "smo_loop_cfg3_traffic.json"),
 }
 
 
