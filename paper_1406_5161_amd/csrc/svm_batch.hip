@@ -978,17 +978,27 @@ __device__ __attribute__((noinline)) void solve_team(BatchShared& sh, unsigned c
                         }
                     }
                 }
-                if (do_shrink) {   // chunks in list order keep the compaction stable and in place
-#pragma unroll
-                    for (int r = 0; r < RPT; ++r) {
-                        int tot;
-                        const int pos = block_scan_keep(keep[r], sh.wc, tot);
-                        if (keep[r]) {
-                            if (res) act_l[newcount + pos] = (uint16_t)rr[r];
-                            else act[newcount + pos] = ii[r];
-                        }
-                        newcount += tot;
+            }
+            if (do_shrink) {
+                // rows the rule removed carry the shrunk bit: one stable in-place compaction of
+                // the list after the pass (each chunk is read before its first barrier and
+                // written only below its own start)
+                __syncthreads();
+                for (int b0 = 0; b0 < nact; b0 += BB) {
+                    const int t = b0 + (int)threadIdx.x;
+                    int r = 0;
+                    bool k = false;
+                    if (t < nact) {
+                        r = res ? (int)act_l[t] : act[t] - seg0;
+                        k = !((res ? st_l[r] : P.status[seg0 + r]) & 8);
                     }
+                    int tot;
+                    const int pos = block_scan_keep(k, sh.wc, tot);
+                    if (k) {
+                        if (res) act_l[newcount + pos] = (uint16_t)r;
+                        else act[newcount + pos] = seg0 + r;
+                    }
+                    newcount += tot;
                 }
             }
             lap(1);

@@ -185,6 +185,47 @@ def test_fp64_trajectory_and_contract(S, case):
     P("  iterations", ref.iterations, "dual rel %.2e decision %.2e" % (rel, worst))
 
 
+def short_rows(n, d, seed):
+    """CSR rows of 1, 2, 3 or 7 nonzeros (so rows start at odd and even element positions and
+    end inside a pair), an odd total, lognormal values, labels from a random sign teacher."""
+    r = np.random.default_rng([1406, 5161, 77, seed])
+    lens = r.choice([1, 2, 3, 7], size=n, p=[0.3, 0.2, 0.3, 0.2])
+    if lens.sum() % 2 == 0:
+        lens[-1] += 1
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    col = np.concatenate([np.sort(r.choice(d, size=k, replace=False)) for k in lens]).astype(np.int32)
+    val = np.exp(r.normal(0.0, 0.5, size=int(rp[-1]))).astype(np.float32)
+    w = r.normal(size=d)
+    score = np.add.reduceat(w[col] * val, rp[:-1])
+    y = np.where(score > np.median(score), 1, -1).astype(np.int8)
+    data = g.SvmData("short_rows_d%d" % d, n, d, "csr", y, row_ptr=rp.astype(np.int32), col=col, val=val)
+    return g.SvmConfig(data.name, data, C=1.0, gamma=0.05, eps=1e-3, shrink_mode=g.SHRINK_MULTI,
+                       shrink_kind=g.KIND_FIXED, shrink_param=2.0)
+
+
+@pytest.mark.parametrize("flags,mode", [(4, 1), (8, 0)], ids=["state_in_lds", "all_in_hbm"])
+@pytest.mark.parametrize("d", [5000, 40000], ids=["column_table", "slot_map"])
+def test_element_pair_stream_on_short_odd_rows(S, d, flags, mode):
+    """Rows streamed from HBM as element pairs: rows of 1-7 nonzeros starting at odd and even
+    positions, an odd total (the last pair holds the zero padding), 8 workgroups, earliest
+    shrinking with multi reconstruction; FP64 kernel values follow the oracle's pairs, FP32
+    meets the dual contract."""
+    cfg = short_rows(3000, d, d)
+    assert cfg.data.nnz % 2 == 1
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP64, trace_cap=100_000, flags=flags, grid_blocks=8)
+    assert out.rc == S.SVM_OK, S.strerror(out.rc)
+    assert S.svm_debug_step_info()[:2] == (mode, 8)
+    ref = O.train_config(cfg, trace_cap=100_000)
+    P("short rows d", d, "mode", mode, "iterations", ref.iterations, "recon", ref.n_recon)
+    assert out.result["iterations"] == ref.iterations
+    assert first_divergence(tr, ref.trace) == -1
+    np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
+    o32, _ = gpu_train(S, cfg, S.SVM_KERNEL_FP32, flags=flags, grid_blocks=8)
+    assert o32.rc == S.SVM_OK
+    assert abs(o32.result["dual_obj"] - ref.dual_obj) <= 1e-6 * abs(ref.dual_obj)
+
+
 @pytest.mark.parametrize("flags,mode", [(0, 2), (4, 1), (8, 0)], ids=["rows_in_lds", "state_in_lds", "all_in_hbm"])
 @pytest.mark.parametrize("case", [
     ("cfg1_n2000", lambda: g.config1()),
