@@ -420,6 +420,83 @@ def test_one_step_from_oracle_state(S):
         np.testing.assert_allclose(f.cpu().numpy(), nxt.f, atol=1e-12)
 
 
+# ------------------------------------------------------------------ degenerate problems
+
+def degenerate_cases():
+    """(name, SvmConfig) of problems that reach the method's special cases: exact duplicate rows
+    with opposite labels (eta = 0, the floor of eq:rho and the end of the box), two samples
+    (the closed form 1 / (1 - K) capped at C), and a few distinct points repeated with mixed
+    labels (every pair is a duplicate or one of a handful of distances)."""
+    r = np.random.default_rng([1406, 5161, 93])
+    out = []
+    base = g.config1(n=600, d=5).data
+    x = base.x.copy()
+    y = base.y.copy()
+    x[300:350] = x[:50]
+    y[300:350] = -y[:50]
+    out.append(("duplicates_opposite_dense", g.SvmConfig("dup_dense", g.SvmData("dup_dense", 600, 5, "dense", y, x=x),
+                                                         C=1.0, gamma=0.2, shrink_mode=g.SHRINK_MULTI,
+                                                         shrink_kind=g.KIND_FIXED, shrink_param=2.0)))
+    c2 = g.config2(n=600).data
+    rp, col = c2.row_ptr.astype(np.int64), c2.col.copy()
+    rows = [col[rp[i]:rp[i + 1]] for i in range(600)]
+    yb = c2.y.copy()
+    for i in range(40):
+        rows[300 + i] = rows[i]
+        yb[300 + i] = -yb[i]
+    rp2 = np.zeros(601, np.int64)
+    np.cumsum([len(t) for t in rows], out=rp2[1:])
+    cc = np.concatenate(rows).astype(np.int32)
+    out.append(("duplicates_opposite_binary", g.SvmConfig(
+        "dup_bits", g.SvmData("dup_bits", 600, 300, "csr", yb, row_ptr=rp2.astype(np.int32), col=cc,
+                              val=np.ones(len(cc), np.float32)), C=1.0, gamma=1.0 / 300)))
+    x2 = np.array([[0.0, 1.0, 2.0], [1.5, -0.5, 0.25]], np.float32)
+    out.append(("two_samples", g.SvmConfig("two", g.SvmData("two", 2, 3, "dense", np.array([1, -1], np.int8), x=x2),
+                                           C=10.0, gamma=0.3)))
+    pts = r.normal(size=(4, 6)).astype(np.float32)
+    idx = r.integers(0, 4, size=400)
+    yf = np.where(r.random(400) < 0.5, 1, -1).astype(np.int8)
+    out.append(("few_distinct_points", g.SvmConfig("few", g.SvmData("few", 400, 6, "dense", yf, x=pts[idx]),
+                                                   C=2.0, gamma=0.5)))
+    return out
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("grid", [1, 8])
+@pytest.mark.parametrize("case", degenerate_cases(), ids=lambda c: c[0])
+def test_degenerate_problems_meet_the_contract(S, case, grid, prec):
+    """Duplicate rows make kernel values and f values tie exactly, so the pair sequence is
+    decided by the last ulp of exp (the device's against the host's) and may part from the
+    oracle's; what is unique is compared instead: the dual (eq:lagdual) to 1e-6, and the KKT
+    conditions (eq:kktterm) of the GPU's alpha on a fresh FP64 recompute of f by the oracle,
+    with the box and the equality constraint.  Two samples have one optimum: alpha equals
+    the closed form 1 / (1 - K) capped at C."""
+    name, cfg = case
+    if cfg.data.n < 8 * grid:
+        grid = 1
+    out, tr = gpu_train(S, cfg, prec, trace_cap=100_000, grid_blocks=grid)
+    assert out.rc == S.SVM_OK, S.strerror(out.rc)
+    ref = O.train_config(cfg, trace_cap=100_000, dual_fresh=True)
+    a, C = out.alpha, cfg.C
+    y = cfg.data.y.astype(np.float64)
+    P(name, "grid", grid, "prec", prec, "iterations", out.result["iterations"], "(oracle", ref.iterations,
+      ") first divergence", first_divergence(tr, ref.trace))
+    assert a.min() >= 0.0 and a.max() <= C and abs(float(np.dot(a, y))) <= 1e-9 * C * cfg.data.n
+    assert abs(out.result["dual_obj"] - ref.dual_obj) <= 1e-6 * abs(ref.dual_obj)
+    f = O.f_full(cfg.data, a, cfg.gamma)
+    free = (a > 0) & (a < C)
+    up = free | ((y > 0) & (a == 0)) | ((y < 0) & (a >= C))
+    low = free | ((y > 0) & (a >= C)) | ((y < 0) & (a == 0))
+    assert f[low].max() - f[up].min() <= 2 * cfg.eps + (1e-9 if prec == 1 else 1e-5)
+    if name == "few_distinct_points":
+        # pairs of identical rows (eta = 0) were selected, so the floor of eq:rho ran on the GPU
+        X = cfg.data.x
+        assert sum(1 for i, j in zip(tr["i_up"], tr["i_low"]) if np.array_equal(X[i], X[j])) > 0
+    if name == "two_samples":
+        k = float(np.exp(-cfg.gamma * np.sum((cfg.data.x[0].astype(np.float64) - cfg.data.x[1]) ** 2)))
+        assert np.abs(a - min(C, 1.0 / (1.0 - k))).max() <= (1e-9 if prec == 1 else 1e-5)
+
+
 # ------------------------------------------------------------------ error paths and caps
 
 def test_error_codes(S):
