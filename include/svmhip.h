@@ -100,7 +100,8 @@ typedef struct {
     int64_t max_iter;         /* iteration cap (> 0); reaching it returns SVM_NOT_CONVERGED */
     int32_t kernel_precision; /* SVM_KERNEL_FP32 | SVM_KERNEL_FP64 */
     uint32_t flags;           /* SVM_FLAG_* */
-    int32_t grid_blocks;      /* 0 = choose automatically; else the number of workgroups of the step
+    int32_t grid_blocks;      /* 0 = choose automatically (the shape svm_autotune recorded for the problem's
+                                 class, else a built-in rule); else the number of workgroups of the step
                                  (svm_train) or of the problem's team (batch / server, at most 64) */
     int32_t lanes_per_row;    /* 0 = choose automatically; CSR lanes per row (1, 2, 4, 8, 16, 32, 64) */
     int32_t head_cols;        /* CSR with d > 12,288 and FP32 kernel values (svm_train): columns kept as dense
@@ -208,7 +209,8 @@ int svm_decision_noalloc(const svm_problem_t* train, const double* alpha, double
  * members can each keep their share of the samples, with its rows, in LDS,
  * when that share is at least 512 samples; else about 1500 samples per
  * workgroup, whose rows stream from HBM while their f, status and active
- * list stay in LDS; params[p].grid_blocks overrides), problems never synchronise
+ * list stay in LDS; a team size recorded by svm_autotune for the problem's class
+ * replaces that rule, and params[p].grid_blocks overrides both), problems never synchronise
  * with each other.  Every problem runs the whole method of svm_train (SMO
  * loop, shrinking, reconstruction, closing recompute) inside its team; alpha
  * and f do not depend on the team size or on the other problems.  alpha[p]
@@ -216,8 +218,10 @@ int svm_decision_noalloc(const svm_problem_t* train, const double* alpha, double
  * (host) the result (grid_blocks = team size, ms_step = device time of the
  * solve).  All problems share one kernel precision.  CSR rows may hold at
  * most 4096 nonzeros and d (dense: d rounded up to 4) at most about 1700
- * (SVM_EUNSUPPORTED beyond).  Lanes per row come from the built-in autotuner
- * unless params[p].lanes_per_row is set.  Returns the first non-OK status. */
+ * (SVM_EUNSUPPORTED beyond).  Lanes per row come from a built-in rule unless
+ * params[p].lanes_per_row is set.  The call allocates the problems' solver
+ * state on the device itself and frees it before returning.  Returns the first
+ * non-OK status. */
 int svm_train_batch(int32_t k, const svm_problem_t* probs, const svm_params_t* params, double* const* alpha,
                     double* const* f, svm_result_t* out, void* stream);
 
