@@ -497,6 +497,50 @@ def test_degenerate_problems_meet_the_contract(S, case, grid, prec):
         assert np.abs(a - min(C, 1.0 / (1.0 - k))).max() <= (1e-9 if prec == 1 else 1e-5)
 
 
+# ------------------------------------------------------------------ the widest supported rows
+
+def widest_rows(d, seed):
+    """CSR rows over the largest column counts the library takes (65,536 for the slot map,
+    65,535 for the dense-head kernel sums): 1,500 rows of 20-60 nonzeros drawn from a narrow
+    band of columns at both ends of the range (ids 0-199 and d-200..d-1, so the largest id
+    occurs and rows overlap), lognormal values, labels from a random sign teacher."""
+    r = np.random.default_rng([1406, 5161, 94, seed])
+    pool = np.concatenate([np.arange(200), np.arange(d - 200, d)])
+    lens = r.integers(20, 61, size=1500)
+    rp = np.zeros(1501, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    col = np.concatenate([np.sort(r.choice(pool, size=k, replace=False)) for k in lens]).astype(np.int32)
+    val = np.exp(r.normal(0.0, 0.5, size=int(rp[-1]))).astype(np.float32)
+    w = r.normal(size=d)
+    y = np.where(np.add.reduceat(w[col] * val, rp[:-1]) > 0, 1, -1).astype(np.int8)
+    data = g.SvmData("widest_d%d" % d, 1500, d, "csr", y, row_ptr=rp.astype(np.int32), col=col, val=val)
+    return g.SvmConfig(data.name, data, C=1.0, gamma=0.1, shrink_mode=g.SHRINK_MULTI, shrink_kind=g.KIND_FIXED,
+                       shrink_param=2.0)
+
+
+@pytest.mark.parametrize("d", [65536, 65535], ids=["slot_map_limit", "dense_head_limit"])
+def test_widest_supported_rows(S, d):
+    """Column ids up to the u16 limit through the element-pair stream, the slot map and (at
+    65,535) the dense-head kernel sums, on 8 workgroups with rows streamed from HBM: FP64
+    kernel values follow the oracle's pairs; FP32 meets the dual contract and its decision
+    values on the training rows stay within the eps band of the oracle's."""
+    cfg = widest_rows(d, d)
+    assert cfg.data.col.max() == d - 1
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP64, trace_cap=100_000, flags=4, grid_blocks=8)
+    assert out.rc == S.SVM_OK, S.strerror(out.rc)
+    ref = O.train_config(cfg, trace_cap=100_000)
+    P("widest d", d, "iterations", ref.iterations, "recon", ref.n_recon, "n_sv", ref.n_sv)
+    assert out.result["iterations"] == ref.iterations
+    assert first_divergence(tr, ref.trace) == -1
+    np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
+    o32, _ = gpu_train(S, cfg, S.SVM_KERNEL_FP32, flags=4, grid_blocks=8)
+    assert o32.rc == S.SVM_OK
+    assert o32.result["head_cols"] == (64 if d == 65535 else 0)
+    assert abs(o32.result["dual_obj"] - ref.dual_obj) <= 1e-6 * abs(ref.dual_obj)
+    f = O.f_full(cfg.data, o32.alpha, cfg.gamma)
+    assert np.abs(o32.f - f).max() <= 1e-4
+
+
 # ------------------------------------------------------------------ error paths and caps
 
 def test_error_codes(S):
