@@ -60,7 +60,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 struct Plan {
     size_t ctl, xpack, bits, fint, status, mask, act, seg, cnt, rec, listw, listz, coef, blkcnt, counts, part,
         sumblk, out6, work, htcnt, hthmap, htbits, hthead, htnrm, httcnt, htmisc, htbhead, htbnrm, httoff, httent,
-        kcache, ktags, col16, val2, total;
+        kcache, ktags, col16, val2, prp, total;
     int64_t cache_rows;   // slots of the kernel-row cache (0: none)
     int tag_grid;         // workgroups the cache tags are sized for
 };
@@ -150,10 +150,12 @@ Plan make_plan(const svm_problem_t* p, const svm_params_t* params, int64_t nnz) 
     const size_t vb = params && params->kernel_precision == SVM_KERNEL_FP64 ? 8 : 4;
     q.kcache = take((size_t)q.cache_rows * n * vb);
     q.ktags = take(sizeof(unsigned long long) * (size_t)q.cache_rows * q.tag_grid);
-    // CSR rows as element pairs for the loop's HBM stream (u16 columns and a copy of the values)
-    const size_t npad = p->layout == SVM_CSR ? (size_t)std::max<int64_t>(nnz, 0) + 2 : 0;
+    // CSR rows as element pairs for the loop's HBM stream (u16 columns and a copy of the values,
+    // every row from an even element: at most nnz + n elements)
+    const size_t npad = p->layout == SVM_CSR ? (size_t)std::max<int64_t>(nnz, 0) + n : 0;
     q.col16 = take(sizeof(uint16_t) * npad);
     q.val2 = take(sizeof(float) * npad);
+    q.prp = take(p->layout == SVM_CSR ? sizeof(int32_t) * (n + 1) : 0);
     q.total = o;
     return q;
 }
@@ -303,6 +305,7 @@ struct Solver {
     uint32_t* bits = nullptr;   // LAY_BITS rows
     uint32_t* col2 = nullptr;   // CSR rows as element pairs (LAY_CSR_TABLE / LAY_CSR_SLOT)
     float* val2 = nullptr;
+    int32_t* prp = nullptr;     // first pair of each row
     HtBufs ht{};                // wide CSR: dense head rows for the kernel sums
     int ht_H = 0;               // head columns in use (0: sparse kernel sums only)
     double t_start = 0;         // host clock at the start of the call
@@ -475,7 +478,7 @@ struct Solver {
         a.bits = bits;
         a.wpr = lay == LAY_BITS ? bits_wpr(d) : 0;
         a.row_ptr = p->row_ptr; a.col = p->col; a.val = p->val;
-        a.col2 = col2; a.val2 = val2;
+        a.col2 = col2; a.val2 = val2; a.prp = prp;
         a.pattern_only = pattern_only ? 1 : 0;
         a.max_row_nnz = max_row_nnz;
         a.y = p->y;
@@ -601,11 +604,11 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
             S.bits = S.at<uint32_t>(S.plan.bits);
             HIP_TRY(launch_pack_bits(p->n, p->d, bits_wpr(p->d), p->row_ptr, p->col, S.bits, s));
         } else {
-            // rows the loop may stream from HBM: u16 column pairs and float2 value pairs
+            // rows the loop may stream from HBM: u16 column pairs and float2 value pairs (packed
+            // below, once the row pointers are on the host)
             S.col2 = S.at<uint32_t>(S.plan.col16);
             S.val2 = S.at<float>(S.plan.val2);
-            HIP_TRY(launch_pack_pairs(nnz, p->col, p->val, S.pattern_only ? 1 : 0,
-                                      reinterpret_cast<uint16_t*>(S.col2), S.val2, s));
+            S.prp = S.at<int32_t>(S.plan.prp);
         }
         if (S.lay == LAY_CSR_SLOT && ht_capable(p) && q->kernel_precision == SVM_KERNEL_FP32 && q->head_cols != -1) {
             // the most frequent columns as dense rows for the matrix cores in the kernel sums
@@ -646,6 +649,16 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
         hrp.resize((size_t)p->n + 1);
         HIP_TRY(hipMemcpyAsync(hrp.data(), p->row_ptr, sizeof(int32_t) * hrp.size(), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (S.col2) {
+            // first pair of every row: rows of odd length take one zero element more
+            std::vector<int32_t> hprp((size_t)p->n + 1);
+            hprp[0] = 0;
+            for (int i = 0; i < p->n; ++i) hprp[i + 1] = hprp[i] + (hrp[i + 1] - hrp[i] + 1) / 2;
+            HIP_TRY(hipMemcpyAsync(S.prp, hprp.data(), sizeof(int32_t) * hprp.size(), hipMemcpyHostToDevice, s));
+            HIP_TRY(launch_pack_pairs(p->n, p->row_ptr, S.prp, p->col, p->val, S.pattern_only ? 1 : 0,
+                                      reinterpret_cast<uint16_t*>(S.col2), S.val2, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
     }
     const int max_mode = (q->flags & SVM_FLAG_NO_LDS_STATE) ? STEP_GLOBAL
                        : (q->flags & SVM_FLAG_NO_LDS_PAYLOAD) ? STEP_LDS_STATE : STEP_LDS_ALL;

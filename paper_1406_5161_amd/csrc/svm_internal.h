@@ -109,10 +109,12 @@ struct StepArgs {
     unsigned long long* tags; // [G][cache_rows]
     int32_t cache_rows;
     uint32_t epoch;           // tag epoch of this launch (> 0; the host zeroes the tags per solve)
-    // CSR rows streamed from HBM: element pairs (2q, 2q+1) of the CSR arrays as one word of two
-    // u16 column ids and two floats (1.0 when all values are 1.0), padded with zeros past nnz
-    const uint32_t* col2;     // [(nnz + 2) / 2]
-    const float* val2;        // [(nnz + 2) / 2 * 2], 8-byte aligned
+    // CSR rows streamed from HBM as element pairs: row i holds pairs prp[i] .. prp[i+1]-1, each
+    // one word of two u16 column ids and two floats (1.0 when all values are 1.0); a row of odd
+    // length ends with a zero element (column 0, value 0)
+    const uint32_t* col2;     // [prp[n]]
+    const float* val2;        // [2 prp[n]], 8-byte aligned
+    const int32_t* prp;       // [n + 1] first pair of each row
 };
 
 // Residency of a workgroup's segment during one launch of the SMO loop:
@@ -196,9 +198,10 @@ hipError_t launch_summary(int n, const double* alpha, const double* f, const int
                           double* out6, hipStream_t s);
 hipError_t launch_check_pattern(int nnz, const float* val, int32_t* flag, hipStream_t s);
 // CSR columns as u16 and values (1.0 where pattern_only) copied into element pairs for the SMO
-// loop's HBM stream, with two zero elements past nnz (d <= 65,536)
-hipError_t launch_pack_pairs(int64_t nnz, const int32_t* col, const float* val, int pattern_only, uint16_t* col16,
-                             float* val2, hipStream_t s);
+// loop's HBM stream: row i from element 2 prp[i], a zero element after a row of odd length
+// (d <= 65,536)
+hipError_t launch_pack_pairs(int n, const int32_t* rp, const int32_t* prp, const int32_t* col, const float* val,
+                             int pattern_only, uint16_t* col16, float* val2, hipStream_t s);
 
 int device_cu_count();
 

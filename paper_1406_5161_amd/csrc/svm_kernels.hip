@@ -842,20 +842,29 @@ hipError_t launch_check_pattern(int nnz, const float* val, int32_t* flag, hipStr
     return hipGetLastError();
 }
 
-__global__ void pack_pairs_kernel(int64_t nnz, const int32_t* __restrict__ col, const float* __restrict__ val,
-                                  int pattern_only, uint16_t* col16, float* val2) {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz + 2; p += (int64_t)gridDim.x * blockDim.x) {
-        const bool in = p < nnz;
-        col16[p] = in ? (uint16_t)col[p] : (uint16_t)0;
-        val2[p] = in ? (pattern_only ? 1.f : val[p]) : 0.f;
+__global__ __launch_bounds__(256) void pack_pairs_kernel(int n, const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ prp,
+                                                         const int32_t* __restrict__ col,
+                                                         const float* __restrict__ val, int pattern_only,
+                                                         uint16_t* col16, float* val2) {
+    const int i = blockIdx.x * 16 + (threadIdx.x >> 4), sub = threadIdx.x & 15;   // 16 threads per row
+    if (i >= n) return;
+    const int p0 = rp[i], len = rp[i + 1] - p0;
+    const int64_t o = 2 * (int64_t)prp[i];
+    for (int k = sub; k < len; k += 16) {
+        col16[o + k] = (uint16_t)col[p0 + k];
+        val2[o + k] = pattern_only ? 1.f : val[p0 + k];
+    }
+    if ((len & 1) && sub == 0) {
+        col16[o + len] = (uint16_t)0;
+        val2[o + len] = 0.f;
     }
 }
 
-hipError_t launch_pack_pairs(int64_t nnz, const int32_t* col, const float* val, int pattern_only, uint16_t* col16,
-                             float* val2, hipStream_t s) {
-    if (nnz < 0) return hipErrorInvalidValue;
-    const int64_t blocks = std::min<int64_t>((nnz + 2 + 255) / 256, 4096);
-    pack_pairs_kernel<<<(unsigned)blocks, 256, 0, s>>>(nnz, col, val, pattern_only, col16, val2);
+hipError_t launch_pack_pairs(int n, const int32_t* rp, const int32_t* prp, const int32_t* col, const float* val,
+                             int pattern_only, uint16_t* col16, float* val2, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    pack_pairs_kernel<<<(n + 15) / 16, 256, 0, s>>>(n, rp, prp, col, val, pattern_only, col16, val2);
     return hipGetLastError();
 }
 

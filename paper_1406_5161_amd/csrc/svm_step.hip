@@ -60,7 +60,7 @@ StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, l
     const bool csr = lay != LAY_DENSE;
     p.meta_off = al16(p.pair_bytes);
     const size_t meta = al16(2 * sizeof(double) * (size_t)nseg_max + sizeof(int) * (size_t)nseg_max +
-                             (csr ? sizeof(int) * ((size_t)nseg_max + 1) : 0) + (size_t)nseg_max);
+                             (csr ? 2 * sizeof(int) * ((size_t)nseg_max + 1) : 0) + (size_t)nseg_max);
     p.pay_off = p.meta_off + meta;
     size_t pay;
     if (csr) pay = al16(sizeof(uint16_t) * (size_t)nnz_seg_max) + (pattern_only ? 0 : sizeof(float) * (size_t)nnz_seg_max);
@@ -123,11 +123,13 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     const int nseg = A.seg_start[blk + 1] - seg0;
     int nrows = A.cnt[blk];
     const int gbase = CSR ? A.row_ptr[seg0] : 0;
+    const int pbase = (CSR && MODE != STEP_LDS_ALL) ? A.prp[seg0] : 0;
     double* F;
     double* AL = nullptr;   // alpha of the segment's rows (LDS modes)
     uint8_t* ST;
     int* L;           // active list: global ids (STEP_GLOBAL) or segment-local indices
     int* OFF = nullptr;
+    int* OFF2 = nullptr;      // CSR rows from HBM: first element pair of each row, segment-relative
     float* XL = nullptr;
     uint32_t* XB = nullptr;   // LAY_BITS rows in LDS
     uint16_t* COLL = nullptr;
@@ -141,7 +143,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         AL = F + A.nseg_max;
         L = reinterpret_cast<int*>(AL + A.nseg_max);
         OFF = L + A.nseg_max;
-        ST = reinterpret_cast<uint8_t*>(OFF + (CSR ? A.nseg_max + 1 : 0));
+        OFF2 = OFF + (CSR ? A.nseg_max + 1 : 0);
+        ST = reinterpret_cast<uint8_t*>(OFF2 + (CSR ? A.nseg_max + 1 : 0));
         for (int li = tid; li < nseg; li += BLOCK) {
             F[li] = A.f[seg0 + li];
             AL[li] = A.alpha[seg0 + li];
@@ -150,6 +153,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         for (int t = tid; t < nrows; t += BLOCK) L[t] = A.act[seg0 + t] - seg0;
         if (CSR)
             for (int li = tid; li <= nseg; li += BLOCK) OFF[li] = A.row_ptr[seg0 + li] - gbase;
+        if (CSR && MODE != STEP_LDS_ALL)
+            for (int li = tid; li <= nseg; li += BLOCK) OFF2[li] = A.prp[seg0 + li] - pbase;
         if constexpr (MODE == STEP_LDS_ALL) {
             if (BITS) {
                 XB = reinterpret_cast<uint32_t*>(smem + A.lds_pay_off);
@@ -478,14 +483,20 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                             sl2 += v * (KT)ul.y;
                         }
                     } else {
-                        // columns and values from HBM as element pairs (2q, 2q+1): one word of
-                        // two u16 ids and one float2 per pair, CB2 pairs loaded before any is
-                        // used; elements of the first and last pair outside the row count zero
+                        // columns and values from HBM as the row's element pairs: one word of two
+                        // u16 ids and one float2 per pair, CB2 pairs loaded before any is used (a
+                        // row of odd length ends with a zero element, which adds nothing)
                         constexpr int CB2 = 5;
-                        const int e0 = gbase + p0, e1 = gbase + p1;
-                        const int q1 = (e1 + 1) >> 1;
+                        int q0, q1;
+                        if constexpr (MODE == STEP_GLOBAL) {
+                            q0 = A.prp[i];
+                            q1 = A.prp[i + 1];
+                        } else {
+                            q0 = pbase + OFF2[li];
+                            q1 = pbase + OFF2[li + 1];
+                        }
                         const float2* v2 = reinterpret_cast<const float2*>(A.val2);
-                        for (int qb = (e0 >> 1) + gl; qb < q1; qb += LPR * CB2) {
+                        for (int qb = q0 + gl; qb < q1; qb += LPR * CB2) {
                             uint32_t cc[CB2];
                             float2 vv[CB2];
 #pragma unroll
@@ -496,11 +507,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                             }
 #pragma unroll
                             for (int u = 0; u < CB2; ++u) {
-                                const int q = qb + u * LPR;
-                                if (q >= q1) break;
-                                const int e = 2 * q;
-                                const KT va = e >= e0 ? (KT)vv[u].x : (KT)0;
-                                const KT vb = e + 1 < e1 ? (KT)vv[u].y : (KT)0;
+                                if (qb + u * LPR >= q1) break;
+                                const KT va = (KT)vv[u].x, vb = (KT)vv[u].y;
                                 const int ca = (int)(cc[u] & 0xffffu), cb = (int)(cc[u] >> 16);
                                 const float2 ua = (LAY == LAY_CSR_TABLE) ? pairv[ca] : pairv[slot[ca]];
                                 const float2 ub = (LAY == LAY_CSR_TABLE) ? pairv[cb] : pairv[slot[cb]];
