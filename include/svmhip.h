@@ -106,7 +106,7 @@ typedef struct {
     int32_t lanes_per_row;    /* 0 = choose automatically; CSR lanes per row (1, 2, 4, 8, 16, 32, 64) */
     int32_t head_cols;        /* CSR with d > 12,288 and FP32 kernel values (svm_train): columns kept as dense
                                  rows for the matrix cores in the reconstruction and recompute sums (Alg. 6),
-                                 the most frequent ones; 0 = automatic (64), 32, 64 or 128; -1 = none (every
+                                 the most frequent ones; 0 = automatic (128), 32, 64 or 128; -1 = none (every
                                  nonzero through the sparse path) */
     int32_t cache_mb;         /* svm_train: MiB of the workspace for a kernel-row cache (0 = none).  Used when
                                  the SMO loop streams rows from HBM (not for rows kept in LDS, not for binary
@@ -187,7 +187,7 @@ int svm_train_shared(const svm_problem_t* x, int32_t k, const int8_t* const* y, 
  * and free it on `stream` (stream-ordered).  Binary CSR rows on both sides
  * (every value 1.0, d <= 1024) are summed through bitsets; CSR with
  * 12,288 < d <= 65,535 and FP32 kernel values through the dense head of the
- * 64 most frequent training columns on the matrix cores plus the sparse tail. */
+ * 128 most frequent training columns on the matrix cores plus the sparse tail. */
 size_t svm_decision_workspace_size(const svm_problem_t* train, const svm_problem_t* queries, int32_t kernel_precision);
 int svm_decision(const svm_problem_t* train, const double* alpha, double beta, double gamma,
                  const svm_problem_t* queries, double* out, int32_t kernel_precision, void* workspace,

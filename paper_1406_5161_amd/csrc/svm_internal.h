@@ -214,7 +214,7 @@ constexpr int HT_SLOTS = 8192;        // LDS hash slots for their columns
 constexpr int HT_MAX_D = 65535;       // column ids fit the hash key
 constexpr int HT_MAX_WORDS = (HT_MAX_D + 32) / 32;   // head-column bitmap words
 constexpr int HT_H_MAX = 128;         // head columns: 32, 64 or 128
-constexpr int HT_H_DEFAULT = 64;
+constexpr int HT_H_DEFAULT = 128;
 
 struct HtArgs {
     int32_t H, d, na, nb;

@@ -1,7 +1,7 @@
 """Kernel sums on the matrix cores, measured alone: decision values (eq:classi) of `nq`
 queries against `nsv` support vectors, the same kernels the gradient reconstruction runs.
 Family "dense": dense-mixture rows (d = 28 by default), `kernel_sum_mfma_kernel`.  Family
-"text": text-like CSR rows (d = 47,000, about 75 nonzeros), `kernel_sum_ht_kernel` (the 64
+"text": text-like CSR rows (d = 47,000, about 75 nonzeros), `kernel_sum_ht_kernel` (the 128
 most frequent columns as dense rows on the matrix cores, the rest as a sparse tail).
 
     python -m paper_1406_5161_amd.ksum_bench [--family dense|text] [--nq N] [--nsv N] [--d D] [--reps 5]
@@ -22,6 +22,7 @@ import numpy as np
 from . import datagen as g
 
 FP32_MATRIX_PEAK_TFLOPS = 157.3
+HEAD_COLS = 128   # the library's default head width of wide CSR kernel sums
 
 
 def main():
@@ -59,7 +60,7 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / a.reps
-    dpad = 64 if text else (a.d + 3) & ~3
+    dpad = HEAD_COLS if text else (a.d + 3) & ~3
     pairs = float(a.nq) * float(a.nsv)
     flops = 2.0 * dpad * pairs
     tflops = flops / (ms * 1e-3) / 1e12

@@ -535,7 +535,7 @@ def test_widest_supported_rows(S, d):
     np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
     o32, _ = gpu_train(S, cfg, S.SVM_KERNEL_FP32, flags=4, grid_blocks=8)
     assert o32.rc == S.SVM_OK
-    assert o32.result["head_cols"] == (64 if d == 65535 else 0)
+    assert o32.result["head_cols"] == (128 if d == 65535 else 0)
     assert abs(o32.result["dual_obj"] - ref.dual_obj) <= 1e-6 * abs(ref.dual_obj)
     f = O.f_full(cfg.data, o32.alpha, cfg.gamma)
     assert np.abs(o32.f - f).max() <= 1e-4
