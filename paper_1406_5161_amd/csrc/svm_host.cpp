@@ -866,11 +866,20 @@ int train_shared_impl(const svm_problem_t* x, int k, const int8_t* const* y, con
     }
     const int lay = sv[0]->lay, kprec = params[0].kernel_precision;
     const int n = x->n, d = x->d;
-    const size_t lds = shared_lds_bytes(lay, d);
+    // about 700 rows per workgroup (at most SHARED_GRID_MAX); each workgroup keeps its segment's
+    // rows, f and status in LDS when they fit
+    int G = std::max(1, std::min(SHARED_GRID_MAX, n <= 4096 ? 1 : (n + 350) / 700));
+    int seg_max = (n + G - 1) / G;
+    const size_t lds_res = shared_lds_bytes(lay, d, seg_max, true);
+    bool res = lds_res <= STEP_LDS_BUDGET && shared_max_blocks(lay, kprec, true, lds_res) >= G;
+    size_t lds = shared_lds_bytes(lay, d, seg_max, res);
     if (lds > STEP_LDS_BUDGET) return SVM_EUNSUPPORTED;
-    const int maxG = std::min(SHARED_GRID_MAX, shared_max_blocks(lay, kprec, lds));
+    const int maxG = std::min(SHARED_GRID_MAX, shared_max_blocks(lay, kprec, res, lds));
     if (maxG < 1) return SVM_EUNSUPPORTED;
-    const int G = std::max(1, std::min(maxG, n <= 4096 ? 1 : (n + 350) / 700));
+    if (G > maxG) {   // only without residency, whose LDS does not depend on the segment
+        G = maxG;
+        seg_max = (n + G - 1) / G;
+    }
     Rec* rec = reinterpret_cast<Rec*>(ws + P.rec);
     unsigned long long* work = reinterpret_cast<unsigned long long*>(ws + P.work);
     std::vector<int> status(k, SVM_OK), rechecks(k, 0);
@@ -882,6 +891,8 @@ int train_shared_impl(const svm_problem_t* x, int k, const int8_t* const* y, con
         a.wpr = lay == LAY_BITS ? bits_wpr(d) : 0;
         a.k = k;
         a.live_mask = running;
+        a.seg_max = seg_max;
+        a.res = res ? 1 : 0;
         a.x = sv[0]->xin;
         a.bits = sv[0]->bits;
         a.rec = rec;

@@ -266,6 +266,8 @@ struct SharedArgs {
     int32_t n, d, dpad, lay;  // lay: LAY_DENSE or LAY_BITS
     int32_t wpr, k;           // bitset words per row; problems
     int32_t live_mask;        // problems this launch advances (bit p)
+    int32_t seg_max;          // rows of the largest workgroup segment
+    int32_t res;              // 1: each workgroup keeps its segment's rows, f and status in LDS
     int32_t pad;
     const float* x;           // dense rows [n][dpad]
     const uint32_t* bits;     // bitset rows [n][wpr]
@@ -275,8 +277,10 @@ struct SharedArgs {
     SharedProb prob[SHARED_MAX];
 };
 hipError_t launch_shared(const SharedArgs& a, int G, int kprec, hipStream_t s);
-int shared_max_blocks(int lay, int kprec, size_t lds);
-size_t shared_lds_bytes(int lay, int d);
+int shared_max_blocks(int lay, int kprec, bool res, size_t lds);
+// dynamic LDS of the lockstep launch: the pair rows of every problem, and with res the
+// segment's rows (bitsets or dense floats), f and status of every problem
+size_t shared_lds_bytes(int lay, int d, int seg_max, bool res);
 
 // ---- shape autotuner (svm_tune.cpp): measured shapes per problem class, per process
 enum : int { TUNE_GRID = 0, TUNE_TEAM = 1 };

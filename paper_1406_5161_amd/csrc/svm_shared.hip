@@ -15,7 +15,13 @@
 
 namespace svm {
 
-template <int LAY, typename KT>
+// bytes of the pair rows of SHARED_MAX problems at the start of the dynamic LDS (16-aligned)
+__host__ __device__ inline size_t shared_pair_bytes(int lay, int wpr, int dpad) {
+    const size_t per = lay == LAY_BITS ? sizeof(uint32_t) * 2 * (size_t)wpr : sizeof(float2) * (size_t)dpad;
+    return (per * SHARED_MAX + 15) & ~(size_t)15;
+}
+
+template <int LAY, typename KT, bool RES>
 __global__ __launch_bounds__(SHARED_BLOCK) void smo_shared_kernel(SharedArgs A) {
     constexpr int BLOCK = SHARED_BLOCK;
     constexpr int KM = SHARED_MAX;
@@ -48,6 +54,37 @@ __global__ __launch_bounds__(SHARED_BLOCK) void smo_shared_kernel(SharedArgs A) 
         }
         s_live[p] = live;
         s_exit[p] = EXIT_NONE;
+    }
+    // RES: this segment's rows, and f and status of every problem, live in LDS for the launch
+    const int segn = seg1 - seg0, smax = A.seg_max;
+    const uint32_t* XB = nullptr;
+    const float* XL = nullptr;
+    double* FL = nullptr;
+    uint8_t* SL = nullptr;
+    if constexpr (RES) {
+        const size_t pair = shared_pair_bytes(LAY, A.wpr, A.dpad);
+        const size_t rows = BITS ? sizeof(uint32_t) * (size_t)smax * A.wpr : sizeof(float) * (size_t)smax * A.dpad;
+        unsigned char* base = smem + pair;
+        FL = reinterpret_cast<double*>(base + ((rows + 15) & ~(size_t)15));
+        SL = reinterpret_cast<uint8_t*>(FL + (size_t)KM * smax);
+        if constexpr (BITS) {
+            uint4* dst = reinterpret_cast<uint4*>(base);
+            const uint4* src = reinterpret_cast<const uint4*>(A.bits + (size_t)seg0 * A.wpr);
+            for (int e = tid; e < segn * (A.wpr / 4); e += BLOCK) dst[e] = src[e];
+            XB = reinterpret_cast<const uint32_t*>(base);
+        } else {
+            float4* dst = reinterpret_cast<float4*>(base);
+            const float4* src = reinterpret_cast<const float4*>(A.x + (size_t)seg0 * A.dpad);
+            for (int e = tid; e < segn * (A.dpad / 4); e += BLOCK) dst[e] = src[e];
+            XL = reinterpret_cast<const float*>(base);
+        }
+        for (int p = 0; p < k; ++p) {
+            if (!((A.live_mask >> p) & 1)) continue;
+            for (int li = tid; li < segn; li += BLOCK) {
+                FL[(size_t)p * smax + li] = A.prob[p].f[seg0 + li];
+                SL[(size_t)p * smax + li] = A.prob[p].status[seg0 + li];
+            }
+        }
     }
     if (tid == 0) s_abort = 0;
     unsigned long long work_rows = 0;
@@ -138,19 +175,33 @@ __global__ __launch_bounds__(SHARED_BLOCK) void smo_shared_kernel(SharedArgs A) 
         for (int p = 0; p < KM; ++p) { cbu[p] = INFINITY; cbl[p] = -INFINITY; ciu[p] = IDX_NONE; cil[p] = IDX_NONE; }
         for (int i = seg0 + tid; i < seg1; i += BLOCK) {
             ++work_rows;
+            // a bitset row is loaded once into registers and serves every live problem
+            constexpr int XW = BITS ? BITS_MAX_D / 128 : 1;   // uint4 words of the widest bitset row
+            uint4 xv[XW];
+            int nn = 0;
+            if constexpr (BITS) {
+                const uint4* xr = reinterpret_cast<const uint4*>(RES ? XB + (size_t)(i - seg0) * A.wpr
+                                                                     : A.bits + (size_t)i * A.wpr);
+#pragma unroll
+                for (int w4 = 0; w4 < XW; ++w4) {
+                    if (w4 >= A.wpr / 4) break;
+                    xv[w4] = xr[w4];
+                    nn += __popc(xv[w4].x) + __popc(xv[w4].y) + __popc(xv[w4].z) + __popc(xv[w4].w);
+                }
+            }
 #pragma unroll
             for (int p = 0; p < KM; ++p) {
                 if (p >= k || !s_live[p]) continue;
                 KT du2, dl2;
                 if constexpr (BITS) {
                     const int wpr = A.wpr;
-                    const uint4* xr = reinterpret_cast<const uint4*>(A.bits + (size_t)i * wpr);
                     const uint4* pu = reinterpret_cast<const uint4*>(pairb + (size_t)2 * wpr * p);
                     const uint4* pl = reinterpret_cast<const uint4*>(pairb + (size_t)2 * wpr * p + wpr);
-                    int nn = 0, su = 0, sl2 = 0;
-                    for (int w4 = 0; w4 < wpr / 4; ++w4) {
-                        const uint4 v = xr[w4], a = pu[w4], b = pl[w4];
-                        nn += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+                    int su = 0, sl2 = 0;
+#pragma unroll
+                    for (int w4 = 0; w4 < XW; ++w4) {
+                        if (w4 >= wpr / 4) break;
+                        const uint4 v = xv[w4], a = pu[w4], b = pl[w4];
                         su += __popc(v.x & a.x) + __popc(v.y & a.y) + __popc(v.z & a.z) + __popc(v.w & a.w);
                         sl2 += __popc(v.x & b.x) + __popc(v.y & b.y) + __popc(v.z & b.z) + __popc(v.w & b.w);
                     }
@@ -159,27 +210,30 @@ __global__ __launch_bounds__(SHARED_BLOCK) void smo_shared_kernel(SharedArgs A) 
                     if (du2 < (KT)0) du2 = (KT)0;
                     if (dl2 < (KT)0) dl2 = (KT)0;
                 } else {
-                    dense_dist<KT>(A.x + (size_t)i * A.dpad, pairv + (size_t)A.dpad * p, A.dpad, du2, dl2);
+                    dense_dist<KT>(RES ? XL + (size_t)(i - seg0) * A.dpad : A.x + (size_t)i * A.dpad,
+                                   pairv + (size_t)A.dpad * p, A.dpad, du2, dl2);
                 }
                 const SharedProb& P = A.prob[p];
                 const int iu = s_iu[p], il = s_il[p];
                 const KT gam = (KT)P.gamma;
                 const double ku = (i == iu) ? 1.0 : (double)kexp(-gam * du2);
                 const double kl = (i == il) ? 1.0 : (double)kexp(-gam * dl2);
+                double* fp = RES ? FL + (size_t)p * smax + (i - seg0) : P.f + i;
+                uint8_t* sp = RES ? SL + (size_t)p * smax + (i - seg0) : P.status + i;
                 double fi;
                 {
 #pragma clang fp contract(off)
-                    fi = P.f[i] + (s_cu[p] * ku + s_cl[p] * kl);
+                    fi = *fp + (s_cu[p] * ku + s_cl[p] * kl);
                 }
-                P.f[i] = fi;
-                uint8_t st = P.status[i];
+                *fp = fi;
+                uint8_t st = *sp;
                 if (i == iu) {
                     st = st_make(s_yu[p] > 0, s_nau[p], P.C);
-                    P.status[i] = st;
+                    *sp = st;
                     st_agent(P.alpha + i, s_nau[p]);
                 } else if (i == il) {
                     st = st_make(s_yl[p] > 0, s_nal[p], P.C);
-                    P.status[i] = st;
+                    *sp = st;
                     st_agent(P.alpha + i, s_nal[p]);
                 }
                 if (st_in_up(st) && better_up(fi, i, cbu[p], ciu[p])) { cbu[p] = fi; ciu[p] = i; }
@@ -281,6 +335,16 @@ __global__ __launch_bounds__(SHARED_BLOCK) void smo_shared_kernel(SharedArgs A) 
         __syncthreads();
     }
     __syncthreads();
+    if constexpr (RES) {
+        // the segment's f and status back for the host phases (recompute, summary)
+        for (int p = 0; p < k; ++p) {
+            if (!((A.live_mask >> p) & 1)) continue;
+            for (int li = tid; li < segn; li += BLOCK) {
+                A.prob[p].f[seg0 + li] = FL[(size_t)p * smax + li];
+                A.prob[p].status[seg0 + li] = SL[(size_t)p * smax + li];
+            }
+        }
+    }
     if (A.work && tid == 0) A.work[blk] = 0;
     __syncthreads();
     if (A.work) atomicAdd(A.work + blk, work_rows);
@@ -295,22 +359,34 @@ __global__ __launch_bounds__(SHARED_BLOCK) void smo_shared_kernel(SharedArgs A) 
     }
 }
 
-size_t shared_lds_bytes(int lay, int d) {
-    const size_t per = lay == LAY_BITS ? sizeof(uint32_t) * 2 * (size_t)bits_wpr(d)
-                                       : sizeof(float2) * (size_t)((d + 3) & ~3);
-    return per * SHARED_MAX;
+size_t shared_lds_bytes(int lay, int d, int seg_max, bool res) {
+    const int wpr = lay == LAY_BITS ? bits_wpr(d) : 0, dpad = (d + 3) & ~3;
+    size_t b = shared_pair_bytes(lay, wpr, dpad);
+    if (res) {
+        const size_t rows = lay == LAY_BITS ? sizeof(uint32_t) * (size_t)seg_max * wpr
+                                            : sizeof(float) * (size_t)seg_max * dpad;
+        b += ((rows + 15) & ~(size_t)15) + (sizeof(double) + 1) * (size_t)SHARED_MAX * seg_max;
+    }
+    return b;
 }
 
-static const void* shared_fn(int lay, int kprec) {
-    if (lay == LAY_BITS)
-        return kprec == SVM_KERNEL_FP64 ? (const void*)smo_shared_kernel<LAY_BITS, double>
-                                        : (const void*)smo_shared_kernel<LAY_BITS, float>;
-    return kprec == SVM_KERNEL_FP64 ? (const void*)smo_shared_kernel<LAY_DENSE, double>
-                                    : (const void*)smo_shared_kernel<LAY_DENSE, float>;
+static const void* shared_fn(int lay, int kprec, bool res) {
+    if (lay == LAY_BITS) {
+        if (res)
+            return kprec == SVM_KERNEL_FP64 ? (const void*)smo_shared_kernel<LAY_BITS, double, true>
+                                            : (const void*)smo_shared_kernel<LAY_BITS, float, true>;
+        return kprec == SVM_KERNEL_FP64 ? (const void*)smo_shared_kernel<LAY_BITS, double, false>
+                                        : (const void*)smo_shared_kernel<LAY_BITS, float, false>;
+    }
+    if (res)
+        return kprec == SVM_KERNEL_FP64 ? (const void*)smo_shared_kernel<LAY_DENSE, double, true>
+                                        : (const void*)smo_shared_kernel<LAY_DENSE, float, true>;
+    return kprec == SVM_KERNEL_FP64 ? (const void*)smo_shared_kernel<LAY_DENSE, double, false>
+                                    : (const void*)smo_shared_kernel<LAY_DENSE, float, false>;
 }
 
-int shared_max_blocks(int lay, int kprec, size_t lds) {
-    const void* fn = shared_fn(lay, kprec);
+int shared_max_blocks(int lay, int kprec, bool res, size_t lds) {
+    const void* fn = shared_fn(lay, kprec, res);
     if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, SHARED_BLOCK, lds) != hipSuccess) return 0;
@@ -318,8 +394,8 @@ int shared_max_blocks(int lay, int kprec, size_t lds) {
 }
 
 hipError_t launch_shared(const SharedArgs& a, int G, int kprec, hipStream_t s) {
-    const void* fn = shared_fn(a.lay, kprec);
-    const size_t lds = shared_lds_bytes(a.lay, a.d);
+    const void* fn = shared_fn(a.lay, kprec, a.res != 0);
+    const size_t lds = shared_lds_bytes(a.lay, a.d, a.seg_max, a.res != 0);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
