@@ -288,7 +288,8 @@ int svm_autotune_reset(void);
  * (n_active ids; order irrelevant), from f, alpha and y (device arrays of the
  * full problem) and C, with the same block/grid reduction as the training
  * loop split over `num_blocks` workgroups (0 = automatic).  Ties go to the
- * lowest sample id; an empty side yields +-inf and id -1.  Outputs are host. */
+ * lowest sample id; an empty side yields +-inf and id -1.  Outputs are host.
+ * Allocates a small device buffer on `stream` for the call. */
 int svm_debug_select(int32_t n_active, const int32_t* active, const double* f, const double* alpha,
                      const int8_t* y, double C, int32_t num_blocks, double* b_up, int32_t* i_up, double* b_low,
                      int32_t* i_low, void* stream);
