@@ -497,6 +497,7 @@ struct Solver {
         a.nnz_seg_max = (int32_t)nnz_seg_max;
         a.lds_meta_off = (int32_t)plan_lds.meta_off;
         a.lds_pay_off = (int32_t)plan_lds.pay_off;
+        a.lds_rec_off = (int32_t)plan_lds.rec_off;
         a.prof = prof_cfg();
         a.cache = kcache;
         a.tags = ktags;
@@ -685,7 +686,7 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
                 const int s0 = (int)(((long long)p->n * b) / G), s1 = (int)(((long long)p->n * (b + 1)) / G);
                 nnz_seg_max = std::max<long long>(nnz_seg_max, hrp[s1] - hrp[s0]);
             }
-        plan = plan_step_lds(S.lay, S.d, S.dpad, S.max_row_nnz, nseg_max, nnz_seg_max, S.pattern_only, max_mode);
+        plan = plan_step_lds(S.lay, S.d, S.dpad, S.max_row_nnz, nseg_max, nnz_seg_max, S.pattern_only, max_mode, G);
         if (plan.total > STEP_LDS_BUDGET) return SVM_EUNSUPPORTED;
         if (p->layout == SVM_CSR && S.lay != LAY_BITS && !q->lanes_per_row) {
             // rows in LDS: few lanes per row (short LDS chains, no cross-lane reduction);

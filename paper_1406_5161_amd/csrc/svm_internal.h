@@ -58,6 +58,7 @@ static_assert(sizeof(Ctl) <= 256, "Ctl must fit in its slot");
 // the CSR extents of the two candidates), so readers need no fence or barrier: a
 // record is complete when all its words carry the current tag.
 constexpr int REC_WORDS = 15;
+constexpr int REC_LDS_STRIDE = 17;     // payload words per record in LDS (odd: no bank conflicts)
 struct Rec {
     unsigned long long w[16];
 };
@@ -97,7 +98,7 @@ struct StepArgs {
     int32_t lds_meta_off;     // byte offset of the per-row state in dynamic LDS
     int32_t lds_pay_off;      // byte offset of the resident row payload
     int32_t nnz_seg_max;      // CSR: nonzeros of the largest segment
-    int32_t pad2;
+    int32_t lds_rec_off;      // byte offset of the records' payload words in dynamic LDS (G > 1)
     unsigned long long* prof; // [PROF_SLOTS] phase times of workgroup 0 (wall-clock ticks), or NULL
     const uint32_t* bits;     // LAY_BITS: rows as bitsets [n][wpr]
     int32_t wpr;
@@ -127,11 +128,11 @@ constexpr int PROF_SLOTS = 8;
 constexpr size_t STEP_LDS_BUDGET = 156 * 1024;
 
 struct StepLds {
-    size_t pair_bytes, meta_off, pay_off, total;
+    size_t pair_bytes, rec_off, meta_off, pay_off, total;
     int mode;
 };
 StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, long long nnz_seg_max,
-                      bool pattern_only, int max_mode);
+                      bool pattern_only, int max_mode, int G);
 
 // Kernel sums: out[a] = sum_b coef[b] * K(A_a, B_b) + bias_a, bias_a = -y_a or -beta.
 struct SumArgs {

@@ -30,13 +30,17 @@ namespace svm {
 
 static size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
 
+// Dynamic LDS of one workgroup: the working pair, the payload words of the G records (G > 1),
+// then, by mode, the segment's per-row state and its rows.
 StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, long long nnz_seg_max,
-                      bool pattern_only, int max_mode) {
+                      bool pattern_only, int max_mode, int G) {
     StepLds p{};
+    const size_t rec = G > 1 ? sizeof(uint32_t) * REC_LDS_STRIDE * (size_t)G : 0;
     if (lay == LAY_BITS) {
         const int wpr = bits_wpr(d);
         p.pair_bytes = sizeof(uint32_t) * 2 * (size_t)wpr;
-        p.meta_off = al16(p.pair_bytes);
+        p.rec_off = al16(p.pair_bytes);
+        p.meta_off = p.rec_off + al16(rec);
         p.pay_off = p.meta_off + al16(2 * sizeof(double) * (size_t)nseg_max + sizeof(int) * (size_t)nseg_max +
                                       (size_t)nseg_max);
         const size_t pay = sizeof(uint32_t) * (size_t)wpr * nseg_max;
@@ -48,7 +52,7 @@ StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, l
             p.total = p.pay_off;
         } else {
             p.mode = STEP_GLOBAL;
-            p.total = p.pair_bytes;
+            p.total = p.meta_off;
         }
         return p;
     }
@@ -58,7 +62,8 @@ StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, l
         p.pair_bytes = sizeof(float2) * (1 + 2 * (size_t)max_row_nnz) + al16(sizeof(uint16_t) * (size_t)d) +
                        sizeof(int) * 2 * (size_t)max_row_nnz;
     const bool csr = lay != LAY_DENSE;
-    p.meta_off = al16(p.pair_bytes);
+    p.rec_off = al16(p.pair_bytes);
+    p.meta_off = p.rec_off + al16(rec);
     const size_t meta = al16(2 * sizeof(double) * (size_t)nseg_max + sizeof(int) * (size_t)nseg_max +
                              (csr ? 2 * sizeof(int) * ((size_t)nseg_max + 1) : 0) + (size_t)nseg_max);
     p.pay_off = p.meta_off + meta;
@@ -73,7 +78,7 @@ StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, l
         p.total = p.pay_off;
     } else {
         p.mode = STEP_GLOBAL;
-        p.total = p.pair_bytes;
+        p.total = p.meta_off;
     }
     return p;
 }
@@ -216,6 +221,21 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
             A.tr_iu[iter] = iu; A.tr_il[iter] = il; A.tr_bu[iter] = bu; A.tr_bl[iter] = bl;
         }
         // ---- 1. the working pair: labels, rows into LDS (alpha came with the records)
+        if constexpr (CACHE) {
+            // kernel rows of the pair from the cache: this workgroup's tags name the sample whose
+            // row (over this segment) each slot holds; looked up by wave 1 while wave 0 (or the
+            // whole workgroup) stages the rows
+            if (tid == 64) {
+                const int S = A.cache_rows;
+                const int su = iu % S, sl = il % S;
+                const unsigned long long* tg = A.tags + (size_t)blk * S;
+                const unsigned long long ep = (unsigned long long)A.epoch << 32;
+                s_cache[0] = su;
+                s_cache[1] = sl;
+                s_cache[2] = ld_agent(tg + su) == (ep | (unsigned)iu);
+                s_cache[3] = ld_agent(tg + sl) == (ep | (unsigned)il);
+            }
+        }
         const int yu = A.y[iu] > 0 ? 1 : -1;
         const int yl = A.y[il] > 0 ? 1 : -1;
         if (LAY == LAY_DENSE) {
@@ -278,6 +298,12 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
             if (ext_l) { pl0 = (int)(unsigned)(ext_l & 0xffffffffull); pl1 = (int)(unsigned)(ext_l >> 32); }
             else { pl0 = A.row_ptr[il]; pl1 = A.row_ptr[il + 1]; }
             const int nu = pu1 - pu0, nl = pl1 - pl0;
+            // each thread's first element of both rows is loaded before the LDS clear, so the
+            // two rows cost one memory round trip
+            int cu0 = 0, cl0 = 0;
+            float vu0 = 0.f, vl0 = 0.f;
+            if (tid < nu) { cu0 = A.col[pu0 + tid]; vu0 = A.pattern_only ? 1.f : A.val[pu0 + tid]; }
+            if (tid < nl) { cl0 = A.col[pl0 + tid]; vl0 = A.pattern_only ? 1.f : A.val[pl0 + tid]; }
             const int npv = s_prev_n;
             if (LAY == LAY_CSR_TABLE) {
                 for (int j = tid; j < npv; j += BLOCK) pairv[prev_cols[j]] = make_float2(0.f, 0.f);
@@ -286,52 +312,52 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
             }
             __syncthreads();
             float* pf = reinterpret_cast<float*>(pairv);
-            if (LAY == LAY_CSR_TABLE) {
-                for (int p = tid; p < nu; p += BLOCK) {
-                    int c = A.col[pu0 + p];
-                    pf[2 * c] = A.pattern_only ? 1.f : A.val[pu0 + p];
-                    prev_cols[p] = c;
-                }
-                for (int p = tid; p < nl; p += BLOCK) {
-                    int c = A.col[pl0 + p];
-                    pf[2 * c + 1] = A.pattern_only ? 1.f : A.val[pl0 + p];
-                    prev_cols[nu + p] = c;
-                }
-            } else {
-                for (int p = tid; p < nu; p += BLOCK) {
-                    int c = A.col[pu0 + p];
+            auto stage_u = [&](int p, int c, float v) {
+                if (LAY == LAY_CSR_TABLE) {
+                    pf[2 * c] = v;
+                } else {
                     slot[c] = (uint16_t)(1 + p);
-                    pairv[1 + p] = make_float2(A.pattern_only ? 1.f : A.val[pu0 + p], 0.f);
-                    prev_cols[p] = c;
+                    pairv[1 + p] = make_float2(v, 0.f);
                 }
-                __syncthreads();
-                for (int p = tid; p < nl; p += BLOCK) {
-                    int c = A.col[pl0 + p];
-                    float v = A.pattern_only ? 1.f : A.val[pl0 + p];
-                    int sl = slot[c];
+                prev_cols[p] = c;
+            };
+            auto stage_l = [&](int p, int c, float v) {
+                if (LAY == LAY_CSR_TABLE) {
+                    pf[2 * c + 1] = v;
+                } else {
+                    const int sl = slot[c];
                     if (sl) {
                         pf[2 * sl + 1] = v;
                     } else {
                         slot[c] = (uint16_t)(1 + nu + p);
                         pairv[1 + nu + p] = make_float2(0.f, v);
                     }
-                    prev_cols[nu + p] = c;
                 }
-            }
+                prev_cols[nu + p] = c;
+            };
+            if (tid < nu) stage_u(tid, cu0, vu0);
+            for (int p = tid + BLOCK; p < nu; p += BLOCK)
+                stage_u(p, A.col[pu0 + p], A.pattern_only ? 1.f : A.val[pu0 + p]);
+            // the slot map needs every column of the up row before the low row looks it up
+            if (LAY == LAY_CSR_SLOT) __syncthreads();
+            if (tid < nl) stage_l(tid, cl0, vl0);
+            for (int p = tid + BLOCK; p < nl; p += BLOCK)
+                stage_l(p, A.col[pl0 + p], A.pattern_only ? 1.f : A.val[pl0 + p]);
             __syncthreads();
             if (tid == 0) s_prev_n = nu + nl;
             if (wid == 0) {
+                // |u|^2, |l|^2 and u.l from the staged rows (the values as loaded, lane-strided)
                 KT su = 0, sl2 = 0, dot = 0;
                 for (int p = lane; p < nu; p += 64) {
-                    KT v = A.pattern_only ? (KT)1 : (KT)A.val[pu0 + p];
+                    const KT v = (KT)((LAY == LAY_CSR_TABLE) ? pf[2 * prev_cols[p]] : pairv[1 + p].x);
                     su += v * v;
                 }
                 for (int p = lane; p < nl; p += 64) {
-                    int c = A.col[pl0 + p];
-                    KT v = A.pattern_only ? (KT)1 : (KT)A.val[pl0 + p];
-                    float uv = (LAY == LAY_CSR_TABLE) ? pairv[c].x : pairv[slot[c]].x;
+                    const int c = prev_cols[nu + p];
+                    const float2 e = (LAY == LAY_CSR_TABLE) ? pairv[c] : pairv[slot[c]];
+                    const KT v = (KT)e.y;
                     sl2 += v * v;
-                    dot += v * (KT)uv;
+                    dot += v * (KT)e.x;
                 }
                 su = wave_sum(su);
                 sl2 = wave_sum(sl2);
@@ -343,20 +369,6 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                     s_pair[1] = (double)su;
                     s_pair[2] = (double)sl2;
                 }
-            }
-        }
-        if constexpr (CACHE) {
-            // kernel rows of the pair from the cache: this workgroup's tags name the sample whose
-            // row (over this segment) each slot holds
-            if (tid == 0) {
-                const int S = A.cache_rows;
-                const int su = iu % S, sl = il % S;
-                const unsigned long long* tg = A.tags + (size_t)blk * S;
-                const unsigned long long ep = (unsigned long long)A.epoch << 32;
-                s_cache[0] = su;
-                s_cache[1] = sl;
-                s_cache[2] = ld_agent(tg + su) == (ep | (unsigned)iu);
-                s_cache[3] = ld_agent(tg + sl) == (ep | (unsigned)il);
             }
         }
         __syncthreads();
@@ -649,31 +661,57 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
             unsigned long long reu = 0, rel = 0;
             long long rcnt = 0;
             int ab = 0;
-            if (tid < G) {
-                const unsigned long long* w = A.rec[par * G + tid].w;
-                unsigned v[REC_WORDS];
+            // every wave polls whole records, four per load instruction (16 lanes per record,
+            // one 128-byte line each; a lane re-reads its word until it carries the tag), and
+            // puts their payload halves into LDS; a wave issues the loads of up to QW groups
+            // of four records before it waits, so the exchange is one memory round trip
+            {
+                constexpr int QW = 4;
+                uint32_t* RW = reinterpret_cast<uint32_t*>(smem + A.lds_rec_off);
+                const int sub = lane >> 4, wd = lane & 15;
                 const unsigned long long t0 = wall_clock64();
-                // with more than 64 records, poll the last word written before reading the
-                // record (whole-record polls by every lane of several waves contend); with at
-                // most 64, poll whole records (one memory round trip fewer)
-                if (G > 64) {
-                    while ((unsigned)(ld_agent(w + REC_WORDS - 1) >> 32) != tg) {
+                for (int q0 = wid; 4 * q0 < G && !ab; q0 += NW * QW) {
+                    unsigned x[QW];
+                    bool ok[QW];
+#pragma unroll
+                    for (int j = 0; j < QW; ++j) {
+                        const int r = 4 * (q0 + NW * j) + sub;
+                        ok[j] = !(r < G && wd < REC_WORDS);
+                        x[j] = 0u;
+                    }
+                    for (;;) {
+                        bool all = true;
+#pragma unroll
+                        for (int j = 0; j < QW; ++j) {
+                            if (!ok[j]) {
+                                const int r = 4 * (q0 + NW * j) + sub;
+                                const unsigned long long y = ld_agent(A.rec[par * G + r].w + wd);
+                                ok[j] = (unsigned)(y >> 32) == tg;
+                                x[j] = (unsigned)(y & 0xffffffffull);
+                            }
+                            all = all && ok[j];
+                        }
+                        if (__all(all)) break;
                         if (wall_clock64() - t0 > A.spin_limit) { ab = 1; break; }
                         __builtin_amdgcn_s_sleep(1);
                     }
-                }
-                for (; !ab;) {
-                    bool ok = true;
 #pragma unroll
-                    for (int k = 0; k < REC_WORDS; ++k) {
-                        const unsigned long long x = ld_agent(w + k);
-                        v[k] = (unsigned)(x & 0xffffffffull);
-                        ok = ok && (unsigned)(x >> 32) == tg;
+                    for (int j = 0; j < QW; ++j) {
+                        const int r = 4 * (q0 + NW * j) + sub;
+                        if (r < G && wd < REC_WORDS) RW[r * REC_LDS_STRIDE + wd] = x[j];
                     }
-                    if (ok) break;
-                    if (wall_clock64() - t0 > A.spin_limit) { ab = 1; break; }
-                    __builtin_amdgcn_s_sleep(1);
                 }
+            }
+            if (__syncthreads_or(ab)) {
+                if (tid == 0) __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                exit_reason = EXIT_ABORT;
+                break;
+            }
+            if (tid < G) {
+                const uint32_t* RW = reinterpret_cast<const uint32_t*>(smem + A.lds_rec_off) + tid * REC_LDS_STRIDE;
+                unsigned v[REC_WORDS];
+#pragma unroll
+                for (int k = 0; k < REC_WORDS; ++k) v[k] = RW[k];
                 rbu = __longlong_as_double((long long)(((unsigned long long)v[1] << 32) | v[0]));
                 rbl = __longlong_as_double((long long)(((unsigned long long)v[3] << 32) | v[2]));
                 riu = (int)v[4];
@@ -683,11 +721,6 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                 ral = __longlong_as_double((long long)(((unsigned long long)v[10] << 32) | v[9]));
                 reu = ((unsigned long long)v[12] << 32) | v[11];
                 rel = ((unsigned long long)v[14] << 32) | v[13];
-            }
-            if (__syncthreads_or(ab)) {
-                if (tid == 0) __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                exit_reason = EXIT_ABORT;
-                break;
             }
             lap(3);
             // reduce (value, id) and the record holding each winner publishes its payload
