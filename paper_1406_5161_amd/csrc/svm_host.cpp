@@ -687,7 +687,15 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
                 nnz_seg_max = std::max<long long>(nnz_seg_max, hrp[s1] - hrp[s0]);
             }
         plan = plan_step_lds(S.lay, S.d, S.dpad, S.max_row_nnz, nseg_max, nnz_seg_max, S.pattern_only, max_mode, G);
-        if (plan.total > STEP_LDS_BUDGET) return SVM_EUNSUPPORTED;
+        if (plan.total > STEP_LDS_BUDGET) {
+            // the records' LDS copy grows with G: where the pair rows leave too little room for
+            // it, fewer workgroups (one workgroup has no records at all)
+            if (G == 1 || plan.rec_off > STEP_LDS_BUDGET || tries > 8) return SVM_EUNSUPPORTED;
+            const size_t rec_room = STEP_LDS_BUDGET - plan.rec_off;
+            const int gfit = (int)(rec_room / (sizeof(uint32_t) * REC_LDS_STRIDE)) - 4;
+            G = std::max(1, std::min(G - 1, gfit));
+            continue;
+        }
         if (p->layout == SVM_CSR && S.lay != LAY_BITS && !q->lanes_per_row) {
             // rows in LDS: few lanes per row (short LDS chains, no cross-lane reduction);
             // rows from HBM: enough lanes for coalesced row reads

@@ -83,6 +83,9 @@ StepLds plan_step_lds(int lay, int d, int dpad, int max_row_nnz, int nseg_max, l
     return p;
 }
 
+// element pairs per lane in one load batch of a CSR row streamed from HBM
+constexpr int STREAM_CB2 = 6;
+
 template <int LAY, typename KT, int LPR, int MODE, bool CACHE>
 __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
     constexpr int BLOCK = STEP_BLOCK;
@@ -155,11 +158,47 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
             AL[li] = A.alpha[seg0 + li];
             ST[li] = A.status[seg0 + li];
         }
-        for (int t = tid; t < nrows; t += BLOCK) L[t] = A.act[seg0 + t] - seg0;
+        if (!(CSR && MODE == STEP_LDS_STATE))
+            for (int t = tid; t < nrows; t += BLOCK) L[t] = A.act[seg0 + t] - seg0;
         if (CSR)
             for (int li = tid; li <= nseg; li += BLOCK) OFF[li] = A.row_ptr[seg0 + li] - gbase;
         if (CSR && MODE != STEP_LDS_ALL)
             for (int li = tid; li <= nseg; li += BLOCK) OFF2[li] = A.prp[seg0 + li] - pbase;
+        if constexpr (CSR && MODE == STEP_LDS_STATE) {
+            // rows that take more than one load batch first, so that every lane group gets about
+            // as many of them (the list's order changes no result: the selection is exact)
+            __syncthreads();
+            const int longp = LPR * STREAM_CB2;
+            int nlong = 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                int at_long = 0, at_short = 0;
+                for (int base = 0; base < nrows; base += BLOCK) {
+                    const int t = base + tid;
+                    const int li = t < nrows ? A.act[seg0 + t] - seg0 : 0;
+                    const bool lg = t < nrows && OFF2[li + 1] - OFF2[li] > longp;
+                    const unsigned long long ml = __ballot(lg), ms = __ballot(t < nrows && !lg);
+                    if (lane == 0) { s_wc[wid] = __popcll(ml); s_i[wid] = __popcll(ms); }
+                    __syncthreads();
+                    int offl = 0, offs = 0, totl = 0, tots = 0;
+                    for (int w = 0; w < NW; ++w) {
+                        const int cl = s_wc[w], cs = s_i[w];
+                        offl += (w < wid) ? cl : 0;
+                        offs += (w < wid) ? cs : 0;
+                        totl += cl;
+                        tots += cs;
+                    }
+                    const unsigned long long below = (1ull << lane) - 1ull;
+                    if (pass == 1 && t < nrows) {
+                        if (lg) L[at_long + offl + __popcll(ml & below)] = li;
+                        else L[nlong + at_short + offs + __popcll(ms & below)] = li;
+                    }
+                    at_long += totl;
+                    at_short += tots;
+                    __syncthreads();
+                }
+                nlong = at_long;
+            }
+        }
         if constexpr (MODE == STEP_LDS_ALL) {
             if (BITS) {
                 XB = reinterpret_cast<uint32_t*>(smem + A.lds_pay_off);
@@ -498,7 +537,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
                         // columns and values from HBM as the row's element pairs: one word of two
                         // u16 ids and one float2 per pair, CB2 pairs loaded before any is used (a
                         // row of odd length ends with a zero element, which adds nothing)
-                        constexpr int CB2 = 5;
+                        constexpr int CB2 = STREAM_CB2;
                         int q0, q1;
                         if constexpr (MODE == STEP_GLOBAL) {
                             q0 = A.prp[i];

@@ -245,7 +245,7 @@ def test_residency_modes_follow_the_same_trajectory(S, case, flags, mode):
     np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
 
 
-@pytest.mark.parametrize("grid", [1, 2, 7, 64, 256])
+@pytest.mark.parametrize("grid", [1, 2, 7, 64, 67, 130, 256])
 def test_grid_size_does_not_change_the_trajectory(S, grid):
     cfg = sub(g.config2(heuristic=g.EARLIEST), 3000)
     out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP64, trace_cap=100_000, grid_blocks=grid)
@@ -541,6 +541,37 @@ def test_widest_supported_rows(S, d):
     assert np.abs(o32.f - f).max() <= 1e-4
 
 
+def test_wide_rows_with_a_long_row_take_fewer_workgroups(S):
+    """Rows up to d = 65,535 with one row of 900 nonzeros: the pair rows' slot map and column
+    lists leave LDS room for the records of about a hundred workgroups, so a request for 224
+    gives fewer (the largest that fits) instead of an error; the FP64 trajectory is still the
+    oracle's."""
+    d = 65535
+    cfg = widest_rows(d, d)
+    r = np.random.default_rng([1406, 5161, 96])
+    dat = cfg.data
+    rp, col, val = dat.row_ptr.astype(np.int64), dat.col, dat.val
+    long_cols = np.sort(r.choice(d, size=900, replace=False)).astype(np.int32)
+    long_vals = np.exp(r.normal(0.0, 0.5, size=900)).astype(np.float32)
+    k = 700   # row k becomes the long row
+    col = np.concatenate([col[:rp[k]], long_cols, col[rp[k + 1]:]])
+    val = np.concatenate([val[:rp[k]], long_vals, val[rp[k + 1]:]])
+    lens = np.diff(rp)
+    lens[k] = 900
+    rp2 = np.zeros(dat.n + 1, np.int64)
+    np.cumsum(lens, out=rp2[1:])
+    cfg.data = g.SvmData("widest_long_row", dat.n, d, "csr", dat.y, row_ptr=rp2.astype(np.int32), col=col, val=val)
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP64, trace_cap=100_000, flags=4, grid_blocks=224)
+    assert out.rc == S.SVM_OK, S.strerror(out.rc)
+    mode, G, L = S.svm_debug_step_info()
+    P("long row: mode", mode, "G", G, "L", L)
+    assert 64 < G < 224
+    ref = O.train_config(cfg, trace_cap=100_000)
+    assert out.result["iterations"] == ref.iterations
+    assert first_divergence(tr, ref.trace) == -1
+    np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
+
+
 # ------------------------------------------------------------------ error paths and caps
 
 def test_error_codes(S):
@@ -618,6 +649,30 @@ def test_wide_csr_loop_shapes_follow_the_oracle(S, text_case, grid, flags, cap, 
     assert out.result["iterations"] == ref.iterations
     assert first_divergence(tr, ref.trace) == -1
     np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
+
+
+@pytest.mark.parametrize("grid", [67, 130, 253])
+def test_wide_csr_loop_on_grids_beyond_one_wave_of_records(S, text_case, grid):
+    """More than 64 workgroups, not a multiple of four: every wave reads its share of the
+    records four per load instruction, the last group partly empty, and the merge combines
+    per-wave results; rows streamed from HBM with their state in LDS (the text-like workload's
+    mode).  The FP64 trajectory is the oracle's pair for pair."""
+    cfg, ref = text_case
+    out, tr = gpu_train(S, cfg, S.SVM_KERNEL_FP64, trace_cap=200_000, flags=4, grid_blocks=grid,
+                        lanes_per_row=8)
+    assert out.rc == S.SVM_OK, S.strerror(out.rc)
+    mode, G, L = S.svm_debug_step_info()
+    P("grid", grid, "-> mode", mode, "G", G, "L", L)
+    assert G == grid and L == 8 and mode == 1
+    assert out.result["iterations"] == ref.iterations
+    assert first_divergence(tr, ref.trace) == -1
+    np.testing.assert_allclose(out.alpha, ref.alpha, atol=1e-9)
+    o32, _ = gpu_train(S, cfg, S.SVM_KERNEL_FP32, flags=4, grid_blocks=grid, lanes_per_row=8)
+    o32b, _ = gpu_train(S, cfg, S.SVM_KERNEL_FP32, flags=4, grid_blocks=8, lanes_per_row=8)
+    # FP32: the grid only spreads the same work, so the trained model is the same bit for bit
+    assert o32.rc == S.SVM_OK and o32b.rc == S.SVM_OK
+    assert o32.result["iterations"] == o32b.result["iterations"]
+    assert np.array_equal(o32.alpha, o32b.alpha)
 
 
 def with_values(cfg, seed=3):
