@@ -286,7 +286,6 @@ struct Solver {
     double* alpha;
     double* f;
     Ctl* ctl;
-    unsigned long long* bar;
     uint8_t* status;
     uint8_t* mask;
     int32_t* act;
@@ -484,7 +483,7 @@ struct Solver {
         a.y = p->y;
         a.alpha = alpha; a.f = f; a.status = status;
         a.act = act; a.seg_start = seg; a.cnt = cnt;
-        a.rec = rec; a.ctl = ctl; a.bar = bar;
+        a.rec = rec; a.ctl = ctl;
         a.C = q->C; a.gamma = q->gamma; a.thr = thr;
         a.max_iter = q->max_iter;
         a.H = H;
@@ -503,7 +502,6 @@ struct Solver {
         a.tags = ktags;
         a.cache_rows = cache_rows;
         a.epoch = ++epoch;   // tags of earlier launches (other active sets) never match
-        HIP_TRY(hipMemsetAsync(bar, 0, sizeof(unsigned long long), s));
         HIP_TRY(hipEventRecord(ev0, s));
         HIP_TRY(launch_step(a, G, lpr, q->kernel_precision, plan_lds.total, s));
         HIP_TRY(hipEventRecord(ev1, s));
@@ -549,7 +547,6 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
     S.alpha = alpha;
     S.f = f_out ? f_out : S.at<double>(S.plan.fint);
     S.ctl = S.at<Ctl>(S.plan.ctl);
-    S.bar = S.at<unsigned long long>(S.plan.ctl + 256);
     S.status = S.at<uint8_t>(S.plan.status);
     S.mask = S.at<uint8_t>(S.plan.mask);
     S.act = S.at<int32_t>(S.plan.act);
@@ -674,7 +671,21 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
     const TuneClass tclass{TUNE_GRID, S.lay, q->kernel_precision, S.pattern_only, q->shrink_mode != SVM_SHRINK_NONE,
                            p->n, p->d};
     if (!G) G = tuned_shape(tclass);   // measured by svm_autotune for this class
-    if (!G) G = p->n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 224), (p->n + 350) / 700));
+    if (!G) {
+        G = p->n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 224), (p->n + 350) / 700));
+        if ((S.lay == LAY_DENSE || S.lay == LAY_BITS) && G == 224 && (p->n + 350) / 700 > 224) {
+            // one lane per row: a lane streams its rows one after another, so where the cap binds
+            // take the smallest grid (up to the CU count) that saves one such round (dense
+            // mixture n = 500,000: 245 workgroups and two rows per lane instead of 224 and three,
+            // 15.1 against 16.1 us per iteration)
+            const long long per = (p->n + G - 1) / G;
+            const long long r = (per + STEP_BLOCK - 1) / STEP_BLOCK;
+            if (r > 1) {
+                const long long g2 = (p->n + (r - 1) * STEP_BLOCK - 1) / ((r - 1) * STEP_BLOCK);
+                if (g2 <= cus) G = (int)g2;
+            }
+        }
+    }
     G = std::min(G, p->n);
     const double avg_nnz = p->layout == SVM_CSR ? (double)hrp[p->n] / (double)p->n : 0.0;
     StepLds plan{};

@@ -80,7 +80,6 @@ struct StepArgs {
     int32_t* cnt;             // [G] active count of each segment
     Rec* rec;                 // [2*G] partial selections, double-buffered by iteration parity
     Ctl* ctl;
-    unsigned long long* bar;  // grid-barrier counter, zeroed before each launch
     double C, gamma, thr;
     int64_t max_iter;
     int64_t H;                // shrink schedule value (0: no shrinking in this launch)

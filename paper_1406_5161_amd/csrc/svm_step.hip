@@ -10,9 +10,9 @@
 //      shrink rule (eq:shrink) on shrink iterations and compacts its active
 //      list in place (Alg. 4), and reduces the two-threshold candidates
 //      (eq:bminmax, lowest sample id on ties);
-//   3. the workgroups publish one record each and meet at a grid barrier --
-//      the paper's Allreduce -- after which every workgroup merges all
-//      records and holds the next pair.
+//   3. the workgroups exchange one record each -- the paper's Allreduce, here
+//      tag-validated words in memory with no grid barrier -- after which every
+//      workgroup merges all records identically and holds the next pair.
 // A workgroup owns a fixed segment of the samples for the whole launch and,
 // when it fits, keeps the segment's per-row state (f, status, active list,
 // CSR offsets) and even its row payload in LDS, so an iteration reads HBM
