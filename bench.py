@@ -9,9 +9,10 @@ rows), labels from a sparse linear teacher with 5% flips; RBF gamma = 1, C = 4, 
 earliest shrinking (random:2) with multi reconstruction.  The inputs are resident in HBM
 before the timed region starts.  With ``--tune``, svm_autotune measures a few grid sizes of
 the SMO loop on the workload's first iterations before the clock starts and the timed solves
-use its choice; by default the built-in rule sets the grid (on the text-like workload the
-trials' 300 uncached iterations favour 256 workgroups, 29.2 against 29.9 us per iteration,
-while whole solves with the row cache favour the rule's 224: 8.83 against 8.99 s).
+use its choice; by default the built-in rule sets the grid (on the text-like workload, as
+measured with an earlier loop, the trials' 300 uncached iterations favour 256 workgroups, 29.2
+against 29.9 us per iteration, while whole solves with the row cache favour the rule's 224:
+8.83 against 8.99 s).
 
 Prints ONE JSON line.  ``value`` is SMO iterations per second over the timed solves;
 ``train_s`` is seconds to KKT at eps = 1e-3.  ``roofline`` is the SMO loop kernel's
@@ -25,7 +26,6 @@ Poisson stream (``--no-serve`` skips it).  ``cpu_baseline`` is the FP64 oracle o
 cores (all of them, and one) on a bounded sample of the same solve.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -63,11 +63,9 @@ LOOP_SOURCES = [os.path.join("paper_1406_5161_amd", "csrc", f)
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in LOOP_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the loop kernel's code, comments removed (as the counter summary takes it)."""
+    from paper_1406_5161_amd.profsum import source_hash
+    return source_hash([os.path.join(ROOT, f) for f in LOOP_SOURCES])
 
 
 def traffic_from_profile(workload):

@@ -102,7 +102,9 @@ typedef struct {
     uint32_t flags;           /* SVM_FLAG_* */
     int32_t grid_blocks;      /* 0 = choose automatically (the shape svm_autotune recorded for the problem's
                                  class, else a built-in rule); else the number of workgroups of the step
-                                 (svm_train) or of the problem's team (batch / server, at most 64) */
+                                 (svm_train; fewer where the device or the LDS cannot hold that many, the
+                                 result's grid_blocks says how many) or of the problem's team (batch /
+                                 server, at most 64) */
     int32_t lanes_per_row;    /* 0 = choose automatically; CSR lanes per row (1, 2, 4, 8, 16, 32, 64) */
     int32_t head_cols;        /* CSR with d > 12,288 and FP32 kernel values (svm_train): columns kept as dense
                                  rows for the matrix cores in the reconstruction and recompute sums (Alg. 6),

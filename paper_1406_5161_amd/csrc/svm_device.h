@@ -1,7 +1,8 @@
 // svm_device.h -- device helpers shared by the kernels of libsvmhip.so:
 // index-set tests on the status byte, the two-threshold reduction with its
-// lowest-index tie-break, the FP64 pair update, the grid barrier and the
-// dense distance of a row to the working pair.
+// lowest-index tie-break, the FP64 pair update, the agent-scope loads and
+// stores of the record exchanges and the dense distance of a row to the
+// working pair.
 #pragma once
 
 #include <hip/hip_runtime.h>

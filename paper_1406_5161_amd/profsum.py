@@ -18,8 +18,9 @@ XCD or shader engine) and prints the per-dispatch totals of the --kernel dispatc
 `traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch, one run each) of a
 kernel into HBM bytes per dispatch, each scaled by the factor that makes the
 same counter of the calibration copy (the copy kernel with the largest value in
-the calibration run, of known size B bytes) read B; --source files are hashed
-so a reader can tell whether the kernel changed since the counters were taken.
+the calibration run, of known size B bytes) read B; the code of the --source files
+(comments removed) is hashed so a reader can tell whether the kernel changed since the
+counters were taken.
 """
 from __future__ import annotations
 
@@ -29,6 +30,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sqlite3
 import statistics
 import sys
@@ -139,11 +141,20 @@ def cmd_pmc(a):
             print("last %d: avg %.6g" % (len(vals), statistics.mean(vals)))
 
 
+def code_text(raw: str) -> str:
+    """A C/C++/HIP source without its comments, trailing blanks and empty lines: what the
+    compiler sees of it, so that editing a comment does not mark counters as stale."""
+    t = re.sub(r"/\*.*?\*/", "", raw, flags=re.S)
+    t = re.sub(r"//[^\n]*", "", t)
+    return "\n".join(ln.rstrip() for ln in t.splitlines() if ln.strip())
+
+
 def source_hash(files):
+    """First 16 hex digits of SHA-256 over the code (comments removed) of the files, in order."""
     h = hashlib.sha256()
     for f in files:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode("utf-8"))
     return h.hexdigest()[:16]
 
 

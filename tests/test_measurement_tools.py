@@ -103,3 +103,17 @@ def test_profsum_traffic_calibration(fake_profiles, tmp_path):
     assert t["fetch_kib_per_dispatch"] == pytest.approx(80.0)
     assert t["hbm_bytes_per_launch"] == pytest.approx(80 * 1024 * 2.0 + 6 * 1024)
     assert t["workload"] == "w"
+
+
+def test_source_hash_ignores_comments_only(tmp_path):
+    """The counter summaries are keyed by a hash of the loop kernel's code: editing a comment
+    keeps it, changing a statement does not."""
+    sys.path.insert(0, ROOT)
+    from paper_1406_5161_amd.profsum import source_hash
+    a = tmp_path / "a.hip"
+    a.write_text("// header\nint f(int x) {\n    return x + 1;   // add one\n}\n/* block\n   comment */\n")
+    h0 = source_hash([str(a)])
+    a.write_text("// a different header\n\nint f(int x) {\n    return x + 1;\n}\n")
+    assert source_hash([str(a)]) == h0
+    a.write_text("int f(int x) {\n    return x + 2;\n}\n")
+    assert source_hash([str(a)]) != h0
