@@ -21,7 +21,9 @@ byte counts below, plus the kernel-row cache values it read or wrote) over its H
 duration; the loop's CSR stream moves 6 of the 8 bytes per nonzero counted there (u16 column
 ids), which ``traffic`` (HBM counters) shows.  ``reconstruction`` gives the kernel sums'
 matrix-core rate.  The text-like workload runs with a 160 GiB kernel-row cache by default
-(``--cache-mb 0`` turns it off).  ``serving`` is the batched / serving comparison on the 256-problem
+(``--cache-mb 0`` turns it off); ``kernel_matrix`` is one more solve with the whole kernel matrix
+computed into that cache before the loop (SVM_FLAG_KERNEL_MATRIX), reported beside the headline.
+``serving`` is the batched / serving comparison on the 256-problem
 Poisson stream (``--no-serve`` skips it).  ``cpu_baseline`` is the FP64 oracle on the host
 cores (all of them, and one) on a bounded sample of the same solve.
 """
@@ -130,6 +132,27 @@ def decision_summary(S, torch, dp, alpha, res, cfg, reps=3):
             "kernel_values_per_s": cfg.queries.n * res.n_sv / (ms * 1e-3)}
 
 
+def kernel_matrix_summary(S, torch, cfg, dp, cache_mb, alpha, f, ws, head):
+    """One more solve of the same problem with SVM_FLAG_KERNEL_MATRIX (after one untimed one):
+    the whole kernel matrix computed into the row cache on the matrix cores before the loop, so
+    the loop stages no pair rows and computes no kernel rows.  Not the headline, which runs every
+    step of the loop; reported beside it."""
+    params = S.params_for(cfg, cache_mb=cache_mb, flags=S.SVM_FLAG_KERNEL_MATRIX)
+    for k in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, r = S.svm_train(dp, params, alpha, f, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        assert rc == S.SVM_OK and r.kernel_matrix == 1, S.strerror(rc)
+        log("kernel matrix %d: %d iterations, %.1f ms (fill %.1f ms, loop %.1f ms, recon %.1f ms)"
+            % (k, r.iterations, t * 1e3, r.ms_kmatrix, r.ms_step, r.ms_recon))
+    return {"flag": "SVM_FLAG_KERNEL_MATRIX", "train_s": t, "iters_per_s": r.iterations / t,
+            "iterations": r.iterations, "n_recon": r.n_recon, "n_sv": r.n_sv, "fill_ms": r.ms_kmatrix,
+            "loop_ms": r.ms_step, "recon_ms": r.ms_recon, "us_per_iter": r.ms_step * 1e3 / max(1, r.iterations),
+            "dual_obj": r.dual_obj, "dual_rel_vs_headline": abs(r.dual_obj - head.dual_obj) / abs(head.dual_obj)}
+
+
 def host_cpu():
     model = "unknown"
     try:
@@ -195,6 +218,8 @@ def main():
                     help="kernel-row cache of the SMO loop in MiB (-1: the workload's default, 0: none)")
     ap.add_argument("--serve-problems", type=int, default=256)
     ap.add_argument("--tune", action="store_true", help="take the loop's grid from svm_autotune (before the clock)")
+    ap.add_argument("--no-kernel-matrix", action="store_true",
+                    help="skip the extra solve with the whole kernel matrix in the row cache")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (the method shards by samples; "
@@ -300,6 +325,8 @@ def main():
     out["reconstruction"] = recon_summary(results, data)
     if cfg.queries is not None:
         out["decision"] = decision_summary(S, torch, dp, alpha, last, cfg)
+    if not args.no_kernel_matrix and args.precision == "fp32" and last.cache_rows == data.n and last.head_cols:
+        out["kernel_matrix"] = kernel_matrix_summary(S, torch, cfg, dp, cache_mb, alpha, f, ws, last)
     del ws   # the training workspace (with its row cache) is not needed past this point
     torch.cuda.empty_cache()
     if not args.no_serve:

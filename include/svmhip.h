@@ -75,6 +75,14 @@ extern "C" {
 #define SVM_FLAG_NO_LDS_PAYLOAD 4u     /* tuning/test: stream row payload from HBM even when it fits in LDS */
 #define SVM_FLAG_NO_LDS_STATE 8u       /* tuning/test: keep per-row state in HBM as well */
 #define SVM_FLAG_NO_BITSETS 16u        /* tuning/test: binary CSR rows as column ids, not bitsets */
+#define SVM_FLAG_KERNEL_MATRIX 32u     /* svm_train, FP32 kernel values, CSR rows with the dense head (see
+                                          head_cols): when cache_mb holds all n rows, the whole kernel matrix
+                                          is computed into the cache on the matrix cores before the loop (the
+                                          reconstruction's kernel sums, storing each value), and every
+                                          iteration reads both kernel rows and K(up, low) from it.  Its values
+                                          come from that kernel's arithmetic, not the loop's, so the FP32
+                                          trajectory is not the one without the flag.  Ignored when the
+                                          conditions do not hold (result.kernel_matrix says whether it ran) */
 
 /* A labelled (or, for queries, unlabelled) sample set.  All pointers are device pointers. */
 typedef struct {
@@ -146,6 +154,9 @@ typedef struct {
     int64_t rows_read;        /* of rows_streamed, those whose row data was read (the rest came from the cache) */
     int64_t cache_values;     /* kernel values read from or written to the row cache */
     int64_t cache_both;       /* iterations whose two kernel rows both came from the cache */
+    int32_t kernel_matrix;    /* 1: the whole kernel matrix was computed into the cache (SVM_FLAG_KERNEL_MATRIX) */
+    int32_t reserved;
+    double ms_kmatrix;        /* time of that computation (HIP events on the call's stream) */
 } svm_result_t;
 
 /* Bytes of device workspace svm_train needs for this problem (256-byte aligned). */

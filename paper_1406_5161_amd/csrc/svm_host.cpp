@@ -323,6 +323,8 @@ struct Solver {
     unsigned long long* ktags = nullptr;
     int cache_rows = 0;
     uint32_t epoch = 0;
+    int kfull = 0;                   // the cache holds the whole kernel matrix
+    double ms_kmatrix = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
     ~Solver() {
         if (ev0) (void)hipEventDestroy(ev0);
@@ -347,6 +349,47 @@ struct Solver {
     int select_all() {
         HIP_TRY(launch_select(G, seg, cnt, act, f, alpha, p->y, q->C, rec + 2 * MAX_GRID, ctl, s));
         return read_ctl();
+    }
+
+    // The whole kernel matrix into the cache (slot b holds K(b, a) for every a) by the head/tail
+    // kernel sums storing their kernel values; left off (the loop computes rows as it goes) when
+    // a tile of rows has more tail nonzeros than the kernel's LDS table.
+    int fill_kernel_matrix() {
+        int rows_t = 0;
+        int rc = ht_tile_rows(n, nullptr, ht.tcnt, ht.misc, s, &rows_t);
+        if (rc) return rc;
+        if (!rows_t) return SVM_OK;
+        HIP_TRY(launch_iota(n, listz, s));
+        HIP_TRY(hipMemsetAsync(coef, 0, sizeof(double) * (size_t)n, s));
+        HtArgs h{};
+        h.H = ht_H; h.d = d; h.na = n; h.nb = n;
+        h.tile_rows = rows_t;
+        h.nsplit = ht_nsplit(n, rows_t, n);
+        h.a_head = ht.head;
+        h.a_rp = p->row_ptr;
+        h.a_col = p->col;
+        h.a_val = p->val;
+        h.a_nrm = ht.nrm;
+        h.alist = nullptr;
+        h.b_head = ht.bhead; h.b_nrm = ht.bnrm; h.b_toff = ht.toff; h.b_tent = ht.tent;
+        h.coef = coef;
+        h.hbits = ht.hbits;
+        h.gamma = q->gamma;
+        h.fx_scale = fx_scale; h.fx_inv = fx_inv;
+        h.part = part;
+        h.kout = reinterpret_cast<float*>(kcache);
+        h.ldk = n;
+        HIP_TRY(hipEventRecord(ev2, s));
+        HIP_TRY(launch_ht_pack(n, ht_H, listz, ht.head, ht.nrm, p->row_ptr, p->col, p->val, ht.hmap, ht.tcnt,
+                               ht.toff, ht.bhead, ht.bnrm, ht.tent, s));
+        HIP_TRY(launch_kernel_sum_ht(h, s));
+        HIP_TRY(hipEventRecord(ev3, s));
+        HIP_TRY(hipEventSynchronize(ev3));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev2, ev3));
+        ms_kmatrix = ms;
+        kfull = 1;
+        return SVM_OK;
     }
 
     // f of the rows in `rows` (count from counts[0] or `nrows`) from the support vectors (Alg. 6).
@@ -501,6 +544,7 @@ struct Solver {
         a.cache = kcache;
         a.tags = ktags;
         a.cache_rows = cache_rows;
+        a.kfull = kfull;
         a.epoch = ++epoch;   // tags of earlier launches (other active sets) never match
         HIP_TRY(hipEventRecord(ev0, s));
         HIP_TRY(launch_step(a, G, lpr, q->kernel_precision, plan_lds.total, s));
@@ -730,6 +774,9 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
         S.ktags = S.at<unsigned long long>(S.plan.ktags);
         S.cache_rows = (int)S.plan.cache_rows;
         HIP_TRY(hipMemsetAsync(S.ktags, 0, sizeof(unsigned long long) * (size_t)S.cache_rows * G, s));
+        if ((q->flags & SVM_FLAG_KERNEL_MATRIX) && S.cache_rows == p->n && S.ht_H &&
+            q->kernel_precision == SVM_KERNEL_FP32)
+            if ((rc = S.fill_kernel_matrix())) return rc;
     }
     last_step_info()[0] = plan.mode;
     last_step_info()[1] = G;
@@ -1009,6 +1056,8 @@ int finish(Solver& S, int status, int n_recon, svm_result_t* out) {
         out->cache_values = (int64_t)S.cache_values;
         out->cache_rows = S.cache_rows;
         out->cache_both = S.h.cache_both;
+        out->kernel_matrix = S.kfull;
+        out->ms_kmatrix = S.ms_kmatrix;
         out->nnz_streamed = (int64_t)S.nnz_streamed;
         out->pattern_only = S.pattern_only ? 1 : 0;
         out->lanes_per_row = S.lpr;

@@ -126,6 +126,17 @@ __global__ void reset_active_kernel(int n, int G, int32_t* seg_start, int32_t* c
     }
 }
 
+__global__ void iota_kernel(int n, int32_t* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = i;
+}
+
+hipError_t launch_iota(int n, int32_t* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    iota_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_active(int n, int G, int32_t* seg_start, int32_t* cnt, int32_t* act, hipStream_t s) {
     int m = n > G + 1 ? n : G + 1;
     reset_active_kernel<<<(m + 255) / 256, 256, 0, s>>>(n, G, seg_start, cnt, act);

@@ -444,7 +444,13 @@ __global__ __launch_bounds__(HT_BLOCK) void kernel_sum_ht_kernel(HtArgs A) {
                         const float dot = dv[i] + (float)((double)tv * fx_inv);
                         float d2 = s_na[row] + nbc - 2.f * dot;
                         d2 = d2 < 0.f ? 0.f : d2;
-                        racc[i] += cbv * (double)kexp(-gam * d2);
+                        const float kv = kexp(-gam * d2);
+                        racc[i] += cbv * (double)kv;
+                        if (A.kout) {
+                            const int a = A.alist ? A.alist[r0 + row] : r0 + row;
+                            const int b = c0 + col;
+                            A.kout[(size_t)b * A.ldk + a] = a == b ? 1.f : kv;
+                        }
                     }
                 }
             }

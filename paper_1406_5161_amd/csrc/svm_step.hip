@@ -250,6 +250,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
             s_pt[PROF_SLOTS] = t;
         }
     };
+    const bool kfull = CACHE && A.kfull;
     __syncthreads();
     lap(6);
 
@@ -263,21 +264,31 @@ __global__ __launch_bounds__(STEP_BLOCK) void smo_loop_kernel(StepArgs A) {
         if constexpr (CACHE) {
             // kernel rows of the pair from the cache: this workgroup's tags name the sample whose
             // row (over this segment) each slot holds; looked up by wave 1 while wave 0 (or the
-            // whole workgroup) stages the rows
+            // whole workgroup) stages the rows.  With the whole kernel matrix in the cache every
+            // row is there and K_ul too: nothing is staged.
             if (tid == 64) {
-                const int S = A.cache_rows;
-                const int su = iu % S, sl = il % S;
-                const unsigned long long* tg = A.tags + (size_t)blk * S;
-                const unsigned long long ep = (unsigned long long)A.epoch << 32;
-                s_cache[0] = su;
-                s_cache[1] = sl;
-                s_cache[2] = ld_agent(tg + su) == (ep | (unsigned)iu);
-                s_cache[3] = ld_agent(tg + sl) == (ep | (unsigned)il);
+                if (kfull) {
+                    s_cache[0] = iu;
+                    s_cache[1] = il;
+                    s_cache[2] = 1;
+                    s_cache[3] = 1;
+                } else {
+                    const int S = A.cache_rows;
+                    const int su = iu % S, sl = il % S;
+                    const unsigned long long* tg = A.tags + (size_t)blk * S;
+                    const unsigned long long ep = (unsigned long long)A.epoch << 32;
+                    s_cache[0] = su;
+                    s_cache[1] = sl;
+                    s_cache[2] = ld_agent(tg + su) == (ep | (unsigned)iu);
+                    s_cache[3] = ld_agent(tg + sl) == (ep | (unsigned)il);
+                }
             }
+            if (kfull && tid == 0) s_pair[0] = (double)reinterpret_cast<const KT*>(A.cache)[(size_t)iu * A.n + il];
         }
         const int yu = A.y[iu] > 0 ? 1 : -1;
         const int yl = A.y[il] > 0 ? 1 : -1;
-        if (LAY == LAY_DENSE) {
+        if (kfull) {
+        } else if (LAY == LAY_DENSE) {
             const float* xu = A.x + (size_t)iu * A.dpad;
             const float* xl = A.x + (size_t)il * A.dpad;
             if constexpr (std::is_same<KT, float>::value) {

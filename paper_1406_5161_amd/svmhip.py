@@ -22,6 +22,7 @@ SVM_DENSE_ROW_MAJOR, SVM_DENSE_FEATURE_MAJOR, SVM_CSR = 0, 1, 2
 SVM_KERNEL_FP32, SVM_KERNEL_FP64 = 0, 1
 SVM_FLAG_WARM_START, SVM_FLAG_NO_FINAL_RECOMPUTE = 1, 2
 SVM_FLAG_NO_LDS_PAYLOAD, SVM_FLAG_NO_LDS_STATE, SVM_FLAG_NO_BITSETS = 4, 8, 16
+SVM_FLAG_KERNEL_MATRIX = 32
 
 EXPORTS = ["svm_train_workspace_size", "svm_train", "svm_train_shared_workspace_size", "svm_train_shared",
            "svm_decision_workspace_size", "svm_decision",
@@ -66,7 +67,8 @@ class svm_result_t(C.Structure):
                 ("nnz_streamed", C.c_int64), ("pattern_only", C.c_int32), ("lanes_per_row", C.c_int32),
                 ("ksum_mfma", C.c_int32), ("ms_ksum", C.c_double), ("recon_pairs", C.c_int64),
                 ("head_cols", C.c_int32), ("cache_rows", C.c_int32), ("rows_read", C.c_int64),
-                ("cache_values", C.c_int64), ("cache_both", C.c_int64)]
+                ("cache_values", C.c_int64), ("cache_both", C.c_int64), ("kernel_matrix", C.c_int32),
+                ("reserved", C.c_int32), ("ms_kmatrix", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
