@@ -179,6 +179,8 @@ hipError_t launch_init_state(int n, const int8_t* y, double C, int warm, double*
                              hipStream_t s);
 hipError_t launch_reset_active(int n, int G, int32_t* seg_start, int32_t* cnt, int32_t* act, hipStream_t s);
 hipError_t launch_iota(int n, int32_t* out, hipStream_t s);
+hipError_t launch_kmat_sum(int na, const int32_t* alist, int nb, const int32_t* blist, const double* coef,
+                           const float* kmat, long long ldk, int nsplit, double* part, hipStream_t s);
 hipError_t launch_select(int G, const int32_t* seg_start, const int32_t* cnt, const int32_t* act, const double* f,
                          const double* alpha, const int8_t* y, double C, Rec* rec, Ctl* ctl, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int G, int lpr, int kprec, size_t lds, hipStream_t s);

@@ -776,6 +776,39 @@ hipError_t launch_kernel_sum(const SumArgs& a, int kprec, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Kernel sums from the whole kernel matrix in memory (K(b, a) at kmat[b * ldk + a]): one thread
+// per target row a, its split of the B list in order, eight matrix rows in flight per thread.
+// The rows of B are read contiguously along a, so a workgroup reads 1 KB per support vector.
+__global__ __launch_bounds__(256) void kmat_sum_kernel(int na, const int32_t* __restrict__ alist, int nb,
+                                                       const int32_t* __restrict__ blist,
+                                                       const double* __restrict__ coef,
+                                                       const float* __restrict__ kmat, long long ldk, double* part) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = (nb + gridDim.y - 1) / gridDim.y;
+    const int b0 = blockIdx.y * per, b1 = min(nb, b0 + per);
+    if (r >= na) return;
+    const int a = alist ? alist[r] : r;
+    double acc = 0.0;
+    int j = b0;
+    for (; j + 8 <= b1; j += 8) {
+        float k[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) k[u] = kmat[(size_t)blist[j + u] * ldk + a];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += coef[j + u] * (double)k[u];
+    }
+    for (; j < b1; ++j) acc += coef[j] * (double)kmat[(size_t)blist[j] * ldk + a];
+    part[(size_t)blockIdx.y * na + r] = acc;
+}
+
+hipError_t launch_kmat_sum(int na, const int32_t* alist, int nb, const int32_t* blist, const double* coef,
+                           const float* kmat, long long ldk, int nsplit, double* part, hipStream_t s) {
+    if (na <= 0) return hipSuccess;
+    const dim3 grid((na + 255) / 256, nsplit);
+    kmat_sum_kernel<<<grid, 256, 0, s>>>(na, alist, nb, blist, coef, kmat, ldk, part);
+    return hipGetLastError();
+}
+
 __global__ void finish_sum_kernel(int na, int nsplit, const double* __restrict__ part, const int32_t* __restrict__ alist,
                                   const int8_t* __restrict__ y, double beta, double* out) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
