@@ -144,7 +144,10 @@ def kernel_matrix_summary(S, torch, cfg, dp, cache_mb, alpha, f, ws, head):
         rc, r = S.svm_train(dp, params, alpha, f, workspace=ws)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        assert rc == S.SVM_OK and r.kernel_matrix == 1, S.strerror(rc)
+        assert rc == S.SVM_OK, S.strerror(rc)
+        if r.kernel_matrix != 1:
+            return {"flag": "SVM_FLAG_KERNEL_MATRIX", "kernel_matrix": 0,
+                    "note": "not filled: a tile of rows has more tail nonzeros than the kernel's LDS table"}
         log("kernel matrix %d: %d iterations, %.1f ms (fill %.1f ms, loop %.1f ms, recon %.1f ms)"
             % (k, r.iterations, t * 1e3, r.ms_kmatrix, r.ms_step, r.ms_recon))
     return {"flag": "SVM_FLAG_KERNEL_MATRIX", "train_s": t, "iters_per_s": r.iterations / t,
