@@ -9,10 +9,8 @@ rows), labels from a sparse linear teacher with 5% flips; RBF gamma = 1, C = 4, 
 earliest shrinking (random:2) with multi reconstruction.  The inputs are resident in HBM
 before the timed region starts.  With ``--tune``, svm_autotune measures a few grid sizes of
 the SMO loop on the workload's first iterations before the clock starts and the timed solves
-use its choice; by default the built-in rule sets the grid (on the text-like workload, as
-measured with an earlier loop, the trials' 300 uncached iterations favour 256 workgroups, 29.2
-against 29.9 us per iteration, while whole solves with the row cache favour the rule's 224:
-8.83 against 8.99 s).
+use its choice; by default the built-in rule sets the grid (one workgroup per CU on the
+text-like workload).
 
 Prints ONE JSON line.  ``value`` is SMO iterations per second over the timed solves;
 ``train_s`` is seconds to KKT at eps = 1e-3.  ``roofline`` is the SMO loop kernel's

@@ -720,30 +720,18 @@ int prepare(Solver& S, const svm_problem_t* p, const svm_params_t* q, double* al
                        : (q->flags & SVM_FLAG_NO_LDS_PAYLOAD) ? STEP_LDS_STATE : STEP_LDS_ALL;
     // Shape rules from per-phase timings of the loop on gfx950: one workgroup (no exchange at
     // all) up to 4096 samples; beyond that about 700 samples per workgroup (at most 11 of the
-    // 16 waves hold a row, under three per SIMD), at most 224 workgroups (every workgroup reads
-    // every record, so the exchange grows with G^2).  Measured at the full active set: sparse
-    // binary n = 50,000 6.42 / 6.29 us per iteration at G = 63 / 72; dense n = 500,000
-    // 18.78 / 18.27 / 18.38 us at G = 192 / 224 / 256.
+    // 16 waves hold a row, under three per SIMD), at most one workgroup per CU.  Measured:
+    // sparse binary n = 50,000 6.42 / 6.29 us per iteration at G = 63 / 72; whole text-like
+    // solves (n = 200,000, row cache) 7.56 / 7.42 / 7.30 / 7.16 / 7.10 s at G = 192 / 208 /
+    // 224 / 240 / 256, the records being read in one memory round trip (with two, the exchange
+    // grew with G^2 and 224 was best); dense n = 500,000 15.1 us per iteration at G = 245
+    // and at 256 (two rows per lane), 16.1 at 224 (three).
     const int cus = std::max(1, device_cu_count());
     int G = q->grid_blocks;
     const TuneClass tclass{TUNE_GRID, S.lay, q->kernel_precision, S.pattern_only, q->shrink_mode != SVM_SHRINK_NONE,
                            p->n, p->d};
     if (!G) G = tuned_shape(tclass);   // measured by svm_autotune for this class
-    if (!G) {
-        G = p->n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 224), (p->n + 350) / 700));
-        if ((S.lay == LAY_DENSE || S.lay == LAY_BITS) && G == 224 && (p->n + 350) / 700 > 224) {
-            // one lane per row: a lane streams its rows one after another, so where the cap binds
-            // take the smallest grid (up to the CU count) that saves one such round (dense
-            // mixture n = 500,000: 245 workgroups and two rows per lane instead of 224 and three,
-            // 15.1 against 16.1 us per iteration)
-            const long long per = (p->n + G - 1) / G;
-            const long long r = (per + STEP_BLOCK - 1) / STEP_BLOCK;
-            if (r > 1) {
-                const long long g2 = (p->n + (r - 1) * STEP_BLOCK - 1) / ((r - 1) * STEP_BLOCK);
-                if (g2 <= cus) G = (int)g2;
-            }
-        }
-    }
+    if (!G) G = p->n <= 4096 ? 1 : std::max(1, std::min(cus, (p->n + 350) / 700));
     G = std::min(G, p->n);
     const double avg_nnz = p->layout == SVM_CSR ? (double)hrp[p->n] / (double)p->n : 0.0;
     StepLds plan{};
@@ -1434,7 +1422,7 @@ int svm_autotune(const svm_problem_t* prob, const svm_params_t* params, int32_t 
     int lay = 0, pattern = 0;
     if (target == SVM_TUNE_GRID) {
         const int cus = std::max(1, device_cu_count());
-        const int g0 = n <= 4096 ? 1 : std::max(1, std::min(std::min(cus, 224), (n + 350) / 700));
+        const int g0 = n <= 4096 ? 1 : std::max(1, std::min(cus, (n + 350) / 700));
         for (int v : {g0 / 2, (3 * g0) / 4, g0, std::min(cus, (5 * g0) / 4), std::min(cus, (3 * g0) / 2)})
             if (v <= n) add(v);
         q.grid_blocks = cand.back();
