@@ -148,9 +148,11 @@ def kernel_matrix_summary(S, torch, cfg, dp, cache_mb, alpha, f, ws, head):
                     "note": "not filled: a tile of rows has more tail nonzeros than the kernel's LDS table"}
         log("kernel matrix %d: %d iterations, %.1f ms (fill %.1f ms, loop %.1f ms, recon %.1f ms)"
             % (k, r.iterations, t * 1e3, r.ms_kmatrix, r.ms_step, r.ms_recon))
+    loop_gbs = algorithmic_bytes(r, cfg.data) / (r.ms_step * 1e-3) / 1e9 if r.ms_step > 0 else None
     return {"flag": "SVM_FLAG_KERNEL_MATRIX", "train_s": t, "iters_per_s": r.iterations / t,
             "iterations": r.iterations, "n_recon": r.n_recon, "n_sv": r.n_sv, "fill_ms": r.ms_kmatrix,
             "loop_ms": r.ms_step, "recon_ms": r.ms_recon, "us_per_iter": r.ms_step * 1e3 / max(1, r.iterations),
+            "loop_algorithmic_GBs": loop_gbs,
             "dual_obj": r.dual_obj, "dual_rel_vs_headline": abs(r.dual_obj - head.dual_obj) / abs(head.dual_obj)}
 
 
